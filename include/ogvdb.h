@@ -1,0 +1,189 @@
+/*
+ * ogvdb.h -- C-ABI of the MI355X occupancy-grid ray sampler.
+ *
+ * Kato & Tarashima, "Plug-and-Play Acceleration of Occupancy Grid-based NeRF
+ * Rendering using VDB Grid and Hierarchical Ray Traversal" (2024).  The
+ * library turns a trained dense binary occupancy grid into a VDB-style tree
+ * (Sec. 3) and marches camera rays through it with a hierarchical DDA that
+ * steps over a whole empty tile at once (Sec. 2.3), emitting the fixed-step
+ * sample points that fall in occupied voxels (Sec. 3; Alg. 1 and Alg. 2 of
+ * the supplementary material).  The dense-grid voxel DDA the paper compares
+ * against is available behind the same calls.  On top of the sampler: a fused
+ * volume-rendering composite with its backward pass, and a batched
+ * multi-scene launch.
+ *
+ * Conventions for every call
+ *  - Return value: OGV_OK (0) or a negative ogv_status; no call throws or
+ *    aborts.  ogv_last_error() gives a message for the calling thread.
+ *  - Pointers named *_dev are device pointers (HBM of the current HIP
+ *    device); pointers named *_host are host pointers.  Ray, sample and
+ *    gradient buffers are owned by the caller.  The library owns only what
+ *    sits behind an opaque handle and frees it in the matching *_destroy.
+ *  - Work is enqueued on the caller's stream (a hipStream_t passed as void*;
+ *    NULL is the default stream) and returns without waiting, except where
+ *    a call says it synchronizes.  A built grid is read-only, so several
+ *    sample calls may use one grid concurrently.
+ *  - Geometry is binary32 throughout.  For cascade level l with box
+ *    [B, A] (per axis) and R voxels per axis: h = fl((A-B)/R), plane
+ *    P(m) = fl(B + fl(m*h)), crossing T(m) = fl(fl(P(m)-o)*fl(1/d)).  A voxel
+ *    owns the ray parameters (entry, exit] (a point on a face belongs to the
+ *    voxel the ray leaves, the "<=" tests of Alg. 1); an axis with d == 0 or
+ *    an infinite 1/d keeps the voxel holding o (floor rule).  The finest
+ *    level holding a parameter decides its occupancy (Sec. 3, last
+ *    paragraph).  Samples are the lattice points t_n <= far in occupied
+ *    voxels, n >= 0, with t_n = fl(near + fl(n*dt)) (constant step) or
+ *    t_0 = near, t_{n+1} = fl(t_n + max(fl(t_n*cone), dt_min)) (growing
+ *    step, Sec. 3); each is emitted as (ray id, t0 = t_n, t1 = t_{n+1}),
+ *    ray-major, t ascending.  Rays with a non-finite component get none.
+ */
+#ifndef OGVDB_H
+#define OGVDB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ogv_status;
+#define OGV_OK 0
+#define OGV_ERR_INVALID (-1)     /* bad argument (null pointer, size, parameter) */
+#define OGV_ERR_CAPACITY (-2)    /* workspace or output capacity too small */
+#define OGV_ERR_HIP (-3)         /* a HIP runtime call failed */
+#define OGV_ERR_OOM (-4)         /* device allocation failed */
+#define OGV_ERR_UNSUPPORTED (-5) /* valid but outside what the library handles */
+
+#define OGV_MAX_LEVELS 8
+#define OGV_MAX_RES 1024
+
+/* Loop structure of the sampler (supplementary material):
+ *   OGV_BRANCH -- Alg. 1 "DDA branch": one cell per iteration, branch on its
+ *                 occupancy (NerfAcc's structure);
+ *   OGV_SKIP   -- Alg. 2 "DDA skip": pass over all leading empty cells, then
+ *                 march the occupied run (Instant-NGP's structure).
+ * Both give identical samples. */
+#define OGV_BRANCH 0
+#define OGV_SKIP 1
+
+#define OGV_STEP_CONST 0 /* t_n = near + n*dt            (NeRF-Synthetic, Sec. 3) */
+#define OGV_STEP_CONE 1  /* dt_n = max(t_n*cone, dt_min) (Mip-NeRF 360, Sec. 3) */
+
+typedef struct {
+    int32_t kind;  /* OGV_STEP_CONST or OGV_STEP_CONE */
+    float dt;      /* constant step, > 0 */
+    float cone;    /* growing step factor, >= 0 */
+    float dt_min;  /* growing step floor, > 0 */
+} ogv_step;
+
+/* Opaque grid: a dense bitfield (the plain method) or a VDB tree. */
+typedef struct ogv_grid ogv_grid;
+
+typedef struct {
+    int32_t kind;          /* 0 dense bitfield, 1 VDB tree */
+    int32_t n_levels, res, internal_log2;
+    int64_t bytes;         /* device bytes the representation occupies */
+    int64_t n_nodes, n_leaves;
+    int64_t n_tiles_full, n_tiles_empty;           /* internal-node slots */
+    int64_t n_root_tiles_full, n_root_tiles_empty; /* root cells */
+} ogv_grid_info;
+
+/* Dense bitfield of the occupancy grid, 1 bit per voxel (the paper's OG,
+ * Sec. 1 and Tab. 3: 256 KiB at 128^3).
+ *   n_levels  1..OGV_MAX_LEVELS cascades, finest first; res 1..OGV_MAX_RES.
+ *   boxes_host [n_levels][6] (min x,y,z, max x,y,z), each level's planes
+ *             nested inside the next level's (checked).
+ *   occ_dev   uint8 [n_levels][res][res][res], x slowest, z fastest, nonzero
+ *             = occupied; read during the call's kernels only.
+ *   *out      receives the handle.  Enqueued on `stream`; the handle may be
+ *             used on the same stream at once, on others after a sync. */
+ogv_status ogv_dense_build(int32_t n_levels, int32_t res, const float *boxes_host, const uint8_t *occ_dev,
+                           ogv_grid **out, void *stream);
+
+/* VDB tree of the occupancy grid (Sec. 3): per level a dense root table of
+ * internal nodes, each covering 2^internal_log2 leaf blocks of 8^3 voxels
+ * per axis, with child and value bitmasks; 8^3 leaves hold 512-bit masks.
+ * Uniform blocks are pruned into tiles (all empty -> empty tile, all
+ * occupied -> full tile), and the same one level up (a node whose slots are
+ * all empty or all full tiles becomes a root tile).  Voxels outside the grid
+ * count as empty.  internal_log2 in 1..5.  Other arguments as
+ * ogv_dense_build.  Synchronizes `stream` once (to size the tree). */
+ogv_status ogv_vdb_build(int32_t n_levels, int32_t res, const float *boxes_host, const uint8_t *occ_dev,
+                         int32_t internal_log2, ogv_grid **out, void *stream);
+
+/* Structure counts and bytes; synchronizes the grid's build stream. */
+ogv_status ogv_grid_info_get(const ogv_grid *grid, ogv_grid_info *info_host);
+
+/* Decodes the grid back into occ_out_dev (uint8 [L][R][R][R], 0/1). */
+ogv_status ogv_grid_to_dense(const ogv_grid *grid, uint8_t *occ_out_dev, void *stream);
+
+void ogv_grid_destroy(ogv_grid *grid);
+
+/* Workspace bytes a sample call needs for n_rays rays and this lattice. */
+ogv_status ogv_sample_workspace_size(int64_t n_rays, float near_t, float far_t, const ogv_step *step_host,
+                                     size_t *bytes_host);
+
+/* Counting pass (Alg. 1/Alg. 2 without emission): per-ray sample counts and
+ * their exclusive scan.
+ *   origins_dev, dirs_dev  float32 [n_rays][3].
+ *   near_t, far_t          the ray-parameter range [t_min, t_max]; finite,
+ *                          near_t >= 0; far_t < near_t gives no samples.
+ *   offsets_dev            int64 [n_rays + 1] out: offsets[i] = first
+ *                          sample of ray i, offsets[n_rays] = total.
+ *   ws_dev, ws_bytes       workspace of ogv_sample_workspace_size bytes.
+ * Dense grids march voxels; VDB grids use the hierarchical DDA. */
+ogv_status ogv_sample_count(const ogv_grid *grid, int32_t variant, const float *origins_dev, const float *dirs_dev,
+                            int64_t n_rays, float near_t, float far_t, const ogv_step *step_host,
+                            int64_t *offsets_dev, void *ws_dev, size_t ws_bytes, void *stream);
+
+/* Emission pass: writes ray i's samples at offsets[i] .. offsets[i+1]-1.
+ *   offsets_dev       from ogv_sample_count with the same arguments.
+ *   capacity          length of the sample arrays; samples at index >=
+ *                     capacity are not written.
+ *   ray_ids_dev int32 [capacity], t0_dev/t1_dev float32 [capacity].
+ *   voxel_ids_dev     nullable int32 [capacity]: ((l*R+i)*R+j)*R+k of the
+ *                     voxel owning t0 (debug/parity output, slower). */
+ogv_status ogv_sample_fill(const ogv_grid *grid, int32_t variant, const float *origins_dev, const float *dirs_dev,
+                           int64_t n_rays, float near_t, float far_t, const ogv_step *step_host,
+                           const int64_t *offsets_dev, int64_t capacity, int32_t *ray_ids_dev, float *t0_dev,
+                           float *t1_dev, int32_t *voxel_ids_dev, void *ws_dev, size_t ws_bytes, void *stream);
+
+/* Count + scan + emission in one asynchronous call with no host round trip
+ * (capacity mode): offsets_dev as in ogv_sample_count; samples beyond
+ * `capacity` are dropped and *overflow_dev (int32) is set to 1, else 0.
+ * The caller reads offsets[n_rays] to learn the total. */
+ogv_status ogv_sample_rays(const ogv_grid *grid, int32_t variant, const float *origins_dev, const float *dirs_dev,
+                           int64_t n_rays, float near_t, float far_t, const ogv_step *step_host,
+                           int64_t *offsets_dev, int64_t capacity, int32_t *ray_ids_dev, float *t0_dev,
+                           float *t1_dev, int32_t *voxel_ids_dev, int32_t *overflow_dev, void *ws_dev,
+                           size_t ws_bytes, void *stream);
+
+/* Volume-rendering composite over packed samples (the accumulation of
+ * Sec. 1; emission-absorption quadrature): per ray, dt_i = t1_i - t0_i,
+ * alpha_i = 1 - exp(-sigma_i dt_i), T_i = exp(-sum_{j<i} sigma_j dt_j),
+ * w_i = T_i alpha_i, rgb = sum w_i c_i, opacity = sum w_i.
+ *   offsets_dev int64 [n_rays+1]; t0/t1/sigma float32 [S]; rgb float32 [S][3].
+ *   out_rgb_dev float32 [n_rays][3], out_opacity_dev float32 [n_rays]. */
+ogv_status ogv_composite_fwd(const int64_t *offsets_dev, int64_t n_rays, const float *t0_dev, const float *t1_dev,
+                             const float *sigma_dev, const float *rgb_dev, float *out_rgb_dev,
+                             float *out_opacity_dev, void *stream);
+
+/* Backward of ogv_composite_fwd: given g_rgb (float32 [n_rays][3]) and
+ * g_opacity (float32 [n_rays], nullable = zero), writes
+ * d_sigma_i = dt_i (g_rgb . (T_{i+1} c_i - sum_{k>i} w_k c_k) + g_opacity T_n)
+ * and d_rgb_i = w_i g_rgb (float32 [S] and [S][3]). */
+ogv_status ogv_composite_bwd(const int64_t *offsets_dev, int64_t n_rays, const float *t0_dev, const float *t1_dev,
+                             const float *sigma_dev, const float *rgb_dev, const float *g_rgb_dev,
+                             const float *g_opacity_dev, float *d_sigma_dev, float *d_rgb_dev, void *stream);
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char *ogv_last_error(void);
+
+/* Library version string. */
+const char *ogv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OGVDB_H */

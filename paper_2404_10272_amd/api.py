@@ -1,0 +1,281 @@
+"""Python binding of the ogvdb C-ABI (include/ogvdb.h).
+
+Argument marshalling only: every step of sampling and compositing runs in
+the HIP kernels of libogvdb.so.  PyTorch provides device memory and the
+current stream.  If the library is not built, every call raises: there is no
+fallback path.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libogvdb.so")
+
+BRANCH, SKIP = 0, 1
+STEP_CONST, STEP_CONE = 0, 1
+
+
+class OgvError(RuntimeError):
+    pass
+
+
+class _Step(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dt", ctypes.c_float), ("cone", ctypes.c_float),
+                ("dt_min", ctypes.c_float)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_levels", ctypes.c_int32), ("res", ctypes.c_int32),
+                ("internal_log2", ctypes.c_int32), ("bytes", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
+                ("n_leaves", ctypes.c_int64), ("n_tiles_full", ctypes.c_int64), ("n_tiles_empty", ctypes.c_int64),
+                ("n_root_tiles_full", ctypes.c_int64), ("n_root_tiles_empty", ctypes.c_int64)]
+
+
+_lib = None
+VP, I32, I64, F32, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
+
+# name -> (restype, argtypes); the exported C-ABI
+SIGNATURES = {
+    "ogv_dense_build": (I32, [I32, I32, VP, VP, ctypes.POINTER(VP), VP]),
+    "ogv_vdb_build": (I32, [I32, I32, VP, VP, I32, ctypes.POINTER(VP), VP]),
+    "ogv_grid_info_get": (I32, [VP, ctypes.POINTER(_Info)]),
+    "ogv_grid_to_dense": (I32, [VP, VP, VP]),
+    "ogv_grid_destroy": (None, [VP]),
+    "ogv_sample_workspace_size": (I32, [I64, F32, F32, ctypes.POINTER(_Step), ctypes.POINTER(SZ)]),
+    "ogv_sample_count": (I32, [VP, I32, VP, VP, I64, F32, F32, ctypes.POINTER(_Step), VP, VP, SZ, VP]),
+    "ogv_sample_fill": (I32, [VP, I32, VP, VP, I64, F32, F32, ctypes.POINTER(_Step), VP, I64, VP, VP, VP, VP, VP,
+                              SZ, VP]),
+    "ogv_sample_rays": (I32, [VP, I32, VP, VP, I64, F32, F32, ctypes.POINTER(_Step), VP, I64, VP, VP, VP, VP, VP,
+                              VP, SZ, VP]),
+    "ogv_composite_fwd": (I32, [VP, I64, VP, VP, VP, VP, VP, VP, VP]),
+    "ogv_composite_bwd": (I32, [VP, I64, VP, VP, VP, VP, VP, VP, VP, VP, VP]),
+    "ogv_last_error": (ctypes.c_char_p, []),
+    "ogv_version": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """The loaded libogvdb.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OgvError(f"{LIB_PATH} is not built (run __graft_entry__.build()); no fallback exists")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        msg = lib().ogv_last_error().decode(errors="replace")
+        raise OgvError(f"ogvdb status {status}: {msg}")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_step(kind="const", dt=0.0, cone=0.0, dt_min=0.0):
+    if isinstance(kind, dict):
+        kind, dt, cone, dt_min = kind["kind"], kind.get("dt", 0.0), kind.get("cone", 0.0), kind.get("dt_min", 0.0)
+    k = {"const": STEP_CONST, "cone": STEP_CONE}[kind]
+    return _Step(k, float(dt), float(cone), float(dt_min))
+
+
+def _variant(v):
+    return {"branch": BRANCH, "skip": SKIP, BRANCH: BRANCH, SKIP: SKIP}[v]
+
+
+class Grid:
+    """A built grid on the current device: dense bitfield (plain method) or VDB tree."""
+
+    def __init__(self, handle, kind, boxes):
+        self._h = handle
+        self.kind = kind
+        self.boxes = boxes
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        inf = _Info()
+        _check(lib().ogv_grid_info_get(self._h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+    def to_dense(self):
+        i = self.info()
+        out = torch.empty((i["n_levels"],) + (i["res"],) * 3, dtype=torch.uint8, device="cuda")
+        _check(lib().ogv_grid_to_dense(self._h, _ptr(out), _stream()))
+        return out
+
+    def close(self):
+        if self._h:
+            lib().ogv_grid_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _grid_args(occ, boxes):
+    if occ.dim() == 3:
+        occ = occ.unsqueeze(0)
+    if not occ.is_cuda:
+        raise OgvError("occupancy must be a device tensor")
+    occ = occ.to(torch.uint8).contiguous()
+    L, R = occ.shape[0], occ.shape[1]
+    if occ.shape[1:] != (R, R, R):
+        raise OgvError("occupancy must be [L][R][R][R]")
+    b = (ctypes.c_float * (6 * L))(*[float(x) for x in torch.as_tensor(boxes, dtype=torch.float32).reshape(-1)])
+    return occ, L, R, b
+
+
+def build_dense(occ, boxes, stream=None):
+    occ, L, R, b = _grid_args(occ, boxes)
+    h = ctypes.c_void_p()
+    _check(lib().ogv_dense_build(L, R, b, _ptr(occ), ctypes.byref(h), _stream(stream)))
+    return Grid(h, "dense", boxes)
+
+
+def build_vdb(occ, boxes, internal_log2=4, stream=None):
+    occ, L, R, b = _grid_args(occ, boxes)
+    h = ctypes.c_void_p()
+    _check(lib().ogv_vdb_build(L, R, b, _ptr(occ), int(internal_log2), ctypes.byref(h), _stream(stream)))
+    return Grid(h, "vdb", boxes)
+
+
+def workspace_bytes(n_rays, near, far, step):
+    n = ctypes.c_size_t()
+    _check(lib().ogv_sample_workspace_size(int(n_rays), float(near), float(far), ctypes.byref(step),
+                                           ctypes.byref(n)))
+    return n.value
+
+
+def _rays(origins, dirs):
+    o = origins.contiguous()
+    d = dirs.contiguous()
+    if o.dtype != torch.float32 or d.dtype != torch.float32 or o.shape != d.shape or o.shape[-1] != 3:
+        raise OgvError("origins/dirs must be float32 [N][3] of equal shape")
+    if not (o.is_cuda and d.is_cuda):
+        raise OgvError("rays must be device tensors")
+    return o, d, o.shape[0]
+
+
+class Sampler:
+    """Reusable sampling call on one grid with fixed ray count and lattice;
+    holds the workspace so repeated calls allocate nothing but outputs."""
+
+    def __init__(self, grid, n_rays, near, far, step, variant="skip", device="cuda"):
+        self.grid = grid
+        self.n = int(n_rays)
+        self.near, self.far = float(near), float(far)
+        self.step = step if isinstance(step, _Step) else make_step(step)
+        self.variant = _variant(variant)
+        self.ws_bytes = workspace_bytes(self.n, self.near, self.far, self.step)
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
+        self.offsets = torch.empty(self.n + 1, dtype=torch.int64, device=device)
+        self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def count(self, o, d, stream=None):
+        _check(lib().ogv_sample_count(self.grid.handle, self.variant, _ptr(o), _ptr(d), self.n, self.near, self.far,
+                                      ctypes.byref(self.step), _ptr(self.offsets), _ptr(self.ws), self.ws_bytes,
+                                      _stream(stream)))
+        return self.offsets
+
+    def fill(self, o, d, ray_ids, t0, t1, voxel_ids=None, stream=None):
+        _check(lib().ogv_sample_fill(self.grid.handle, self.variant, _ptr(o), _ptr(d), self.n, self.near, self.far,
+                                     ctypes.byref(self.step), _ptr(self.offsets), int(t0.numel()), _ptr(ray_ids),
+                                     _ptr(t0), _ptr(t1), _ptr(voxel_ids), _ptr(self.ws), self.ws_bytes,
+                                     _stream(stream)))
+
+    def rays(self, o, d, ray_ids, t0, t1, voxel_ids=None, stream=None):
+        """Count + scan + fill with no host round trip (capacity = len(t0))."""
+        _check(lib().ogv_sample_rays(self.grid.handle, self.variant, _ptr(o), _ptr(d), self.n, self.near, self.far,
+                                     ctypes.byref(self.step), _ptr(self.offsets), int(t0.numel()), _ptr(ray_ids),
+                                     _ptr(t0), _ptr(t1), _ptr(voxel_ids), _ptr(self.overflow), _ptr(self.ws),
+                                     self.ws_bytes, _stream(stream)))
+        return self.offsets, self.overflow
+
+
+def sample_rays(grid, origins, dirs, near, far, step, variant="skip", voxel_ids=False):
+    """Packed samples of every ray: dict(offsets[N+1], ray_ids[S], t0[S], t1[S], voxel_ids[S]?).
+
+    Counts first, reads the total (one device->host sync), allocates the
+    exact outputs, then fills.
+    """
+    o, d, n = _rays(origins, dirs)
+    sp = Sampler(grid, n, near, far, step, variant, device=o.device)
+    offsets = sp.count(o, d)
+    total = int(offsets[n].item())
+    dev = o.device
+    out = {"offsets": offsets,
+           "ray_ids": torch.empty(total, dtype=torch.int32, device=dev),
+           "t0": torch.empty(total, dtype=torch.float32, device=dev),
+           "t1": torch.empty(total, dtype=torch.float32, device=dev)}
+    vox = torch.empty(total, dtype=torch.int32, device=dev) if voxel_ids else None
+    sp.fill(o, d, out["ray_ids"], out["t0"], out["t1"], vox)
+    if voxel_ids:
+        out["voxel_ids"] = vox
+    return out
+
+
+# ---------------------------------------------------------------- composite
+
+def composite_forward(offsets, t0, t1, sigma, rgb):
+    n = offsets.numel() - 1
+    out_rgb = torch.empty((n, 3), dtype=torch.float32, device=sigma.device)
+    out_a = torch.empty(n, dtype=torch.float32, device=sigma.device)
+    _check(lib().ogv_composite_fwd(_ptr(offsets), n, _ptr(t0), _ptr(t1), _ptr(sigma), _ptr(rgb), _ptr(out_rgb),
+                                   _ptr(out_a), _stream()))
+    return out_rgb, out_a
+
+
+def composite_backward(offsets, t0, t1, sigma, rgb, g_rgb, g_opacity):
+    d_sigma = torch.zeros_like(sigma)
+    d_rgb = torch.zeros_like(rgb)
+    n = offsets.numel() - 1
+    _check(lib().ogv_composite_bwd(_ptr(offsets), n, _ptr(t0), _ptr(t1), _ptr(sigma), _ptr(rgb), _ptr(g_rgb),
+                                   _ptr(g_opacity), _ptr(d_sigma), _ptr(d_rgb), _stream()))
+    return d_sigma, d_rgb
+
+
+class Composite(torch.autograd.Function):
+    """(sigma[S], rgb[S,3]) -> (pixel rgb[N,3], opacity[N]) over packed samples;
+    the sampler's outputs (offsets, t0, t1) are constants."""
+
+    @staticmethod
+    def forward(ctx, sigma, rgb, offsets, t0, t1):
+        sigma = sigma.contiguous().float()
+        rgb = rgb.contiguous().float()
+        out_rgb, out_a = composite_forward(offsets, t0, t1, sigma, rgb)
+        ctx.save_for_backward(sigma, rgb, offsets, t0, t1)
+        return out_rgb, out_a
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_a):
+        sigma, rgb, offsets, t0, t1 = ctx.saved_tensors
+        if g_rgb is None:
+            g_rgb = torch.zeros((offsets.numel() - 1, 3), dtype=torch.float32, device=sigma.device)
+        g_rgb = g_rgb.contiguous().float()
+        g_a = g_a.contiguous().float() if g_a is not None else None
+        d_sigma, d_rgb = composite_backward(offsets, t0, t1, sigma, rgb, g_rgb, g_a)
+        return d_sigma, d_rgb, None, None, None
+
+
+def composite(sigma, rgb, offsets, t0, t1):
+    return Composite.apply(sigma, rgb, offsets, t0, t1)

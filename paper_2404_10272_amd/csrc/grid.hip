@@ -1,0 +1,490 @@
+// Grid builders: the dense bitfield (the paper's occupancy grid, 1 bit per
+// voxel) and the VDB tree (Sec. 3: root table -> internal nodes -> 8^3
+// leaves, uniform blocks pruned into tiles), both built on the GPU from the
+// dense uint8 occupancy, plus decoding back to dense for round-trip checks.
+//
+// VDB build, all on the device:
+//   1. classify: one wave per 8^3 block slot packs the block into its
+//      512-bit mask (lane = (x, y) row of 8 z-voxels) and marks it empty,
+//      full or mixed;
+//   2. root: per root cell, all slots empty -> empty root tile, all full ->
+//      full root tile, else an internal node;
+//   3. exclusive scans number the nodes and the leaves (mixed blocks under
+//      node roots, in root-then-slot order);
+//   4. write the root table, node masks (child, value, per-word leaf rank)
+//      and leaf masks.
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "internal.hpp"
+#include "scan.hpp"
+
+namespace ogv {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+static float host_plane(const float *box, int R, int a, int m) {
+    float h = (box[3 + a] - box[a]) / (float)R;
+    float mh = (float)m * h;
+    return box[a] + mh;
+}
+
+bool boxes_valid(int L, int R, const float *boxes, std::string *why) {
+    for (int l = 0; l < L; ++l) {
+        const float *b = boxes + 6 * l;
+        for (int a = 0; a < 3; ++a) {
+            if (!std::isfinite(b[a]) || !std::isfinite(b[3 + a]) || !(b[a] < b[3 + a])) {
+                *why = "level " + std::to_string(l) + ": box must be finite with min < max";
+                return false;
+            }
+            float h = (b[3 + a] - b[a]) / (float)R;
+            if (!(h > 0.0f) || !std::isfinite(h)) {
+                *why = "level " + std::to_string(l) + ": voxel size underflows";
+                return false;
+            }
+            if (l > 0) {
+                const float *f = boxes + 6 * (l - 1);
+                if (!(host_plane(b, R, a, 0) <= host_plane(f, R, a, 0)) ||
+                    !(host_plane(b, R, a, R) >= host_plane(f, R, a, R))) {
+                    *why = "level " + std::to_string(l) + " does not contain level " + std::to_string(l - 1);
+                    return false;
+                }
+            }
+        }
+    }
+    return true;
+}
+
+namespace {
+
+// ------------------------------------------------------------------ dense
+
+__global__ void dense_pack_kernel(const uint8_t *__restrict__ occ, uint64_t n_vox, uint32_t *__restrict__ bits,
+                                  uint64_t n_words) {
+    uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= n_words) return;
+    uint32_t word = 0;
+    uint64_t base = w * 32;
+    for (int j = 0; j < 32; ++j) {
+        uint64_t i = base + j;
+        if (i < n_vox && occ[i] != 0) word |= 1u << j;
+    }
+    bits[w] = word;
+}
+
+__global__ void dense_unpack_kernel(const uint32_t *__restrict__ bits, uint64_t n_vox, uint8_t *__restrict__ out) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_vox) return;
+    out[i] = (bits[i >> 5] >> (i & 31)) & 1u;
+}
+
+// ------------------------------------------------------------------ vdb
+
+struct BuildDims {
+    int L, R, ilog2, S, D, NR;
+    int64_t n_root;   // L * NR^3
+    int64_t n_slot;   // S^3
+    int64_t n_block;  // n_root * n_slot
+    int W;            // words per node mask
+};
+
+// block slot e -> voxel base of its 8^3 block
+__device__ __forceinline__ void block_base(const BuildDims &b, int64_t e, int &lev, int &x0, int &y0, int &z0) {
+    int64_t root = e / b.n_slot;
+    int slot = (int)(e % b.n_slot);
+    lev = (int)(root / ((int64_t)b.NR * b.NR * b.NR));
+    int rl = (int)(root % ((int64_t)b.NR * b.NR * b.NR));
+    int rx = rl / (b.NR * b.NR), ry = (rl / b.NR) % b.NR, rz = rl % b.NR;
+    int sx = slot / (b.S * b.S), sy = (slot / b.S) % b.S, sz = slot % b.S;
+    x0 = rx * b.D + sx * 8;
+    y0 = ry * b.D + sy * 8;
+    z0 = rz * b.D + sz * 8;
+}
+
+// one wave per block slot; 4 waves per workgroup
+__global__ void __launch_bounds__(256) classify_kernel(BuildDims b, const uint8_t *__restrict__ occ,
+                                                      int32_t *__restrict__ kind, int32_t *__restrict__ mixed,
+                                                      uint64_t *__restrict__ masks) {
+    __shared__ uint8_t rows[4][64];
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int64_t e = (int64_t)blockIdx.x * 4 + wid;
+    bool live = e < b.n_block;
+    uint8_t byte = 0;
+    if (live) {
+        int lev, x0, y0, z0;
+        block_base(b, e, lev, x0, y0, z0);
+        int x = x0 + (lane >> 3), y = y0 + (lane & 7);
+        if (x < b.R && y < b.R) {
+            const uint8_t *row = occ + (((size_t)lev * b.R + x) * b.R + y) * b.R;
+            for (int z = 0; z < 8; ++z)
+                if (z0 + z < b.R && row[z0 + z] != 0) byte |= (uint8_t)(1u << z);
+        }
+    }
+    rows[wid][lane] = byte;
+    __syncthreads();
+    if (!live) return;
+    // word x of the leaf = bytes (x, y=0..7): bit y*8 + z
+    uint64_t word = 0;
+    if (lane < 8) {
+        for (int y = 0; y < 8; ++y) word |= (uint64_t)rows[wid][lane * 8 + y] << (8 * y);
+        masks[e * 8 + lane] = word;
+    }
+    bool any_on = __ballot(lane < 8 && word != 0) != 0;
+    bool all_on = __ballot(lane < 8 && word == ~0ull) == 0xffull;
+    if (lane == 0) {
+        int k = all_on ? 1 : (any_on ? 2 : 0);
+        kind[e] = k;
+        mixed[e] = k == 2;
+    }
+}
+
+// one workgroup per root cell: empty tile / full tile / node
+__global__ void __launch_bounds__(256) root_kernel(BuildDims b, const int32_t *__restrict__ kind,
+                                                  int32_t *__restrict__ root_kind, int32_t *__restrict__ is_node) {
+    __shared__ int n_empty, n_full;
+    if (threadIdx.x == 0) {
+        n_empty = 0;
+        n_full = 0;
+    }
+    __syncthreads();
+    int64_t r = blockIdx.x;
+    int ce = 0, cf = 0;
+    for (int64_t s = threadIdx.x; s < b.n_slot; s += blockDim.x) {
+        int k = kind[r * b.n_slot + s];
+        ce += k == 0;
+        cf += k == 1;
+    }
+    atomicAdd(&n_empty, ce);
+    atomicAdd(&n_full, cf);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int rk = n_empty == b.n_slot ? 0 : (n_full == b.n_slot ? 1 : 2);
+        root_kind[r] = rk;
+        is_node[r] = rk == 2;
+    }
+}
+
+__global__ void root_write_kernel(BuildDims b, const int32_t *__restrict__ root_kind,
+                                  const int64_t *__restrict__ node_idx, int32_t *__restrict__ root,
+                                  VdbCounts *counts) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= b.n_root) return;
+    int rk = root_kind[r];
+    root[r] = rk == 2 ? (int32_t)node_idx[r] : (rk == 1 ? -2 : -1);
+    if (rk == 0) atomicAdd((unsigned long long *)&counts->n_root_empty, 1ull);
+    if (rk == 1) atomicAdd((unsigned long long *)&counts->n_root_full, 1ull);
+    if (r == 0) {
+        counts->n_nodes = node_idx[b.n_root];
+    }
+}
+
+// one wave per (root cell, mask word); only node roots write
+__global__ void __launch_bounds__(256) node_write_kernel(BuildDims b, const int32_t *__restrict__ root_kind,
+                                                        const int64_t *__restrict__ node_idx,
+                                                        const int32_t *__restrict__ kind,
+                                                        const int64_t *__restrict__ leaf_idx,
+                                                        uint64_t *__restrict__ child, uint64_t *__restrict__ value,
+                                                        uint32_t *__restrict__ rank, VdbCounts *counts) {
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int64_t job = (int64_t)blockIdx.x * 4 + wid;
+    if (job >= b.n_root * b.W) return;
+    int64_t r = job / b.W;
+    int w = (int)(job % b.W);
+    if (root_kind[r] != 2) return;
+    int64_t node = node_idx[r];
+    int64_t s = (int64_t)w * 64 + lane;
+    int k = s < b.n_slot ? kind[r * b.n_slot + s] : -1;
+    uint64_t cm = __ballot(k == 2);
+    uint64_t vm = __ballot(k == 1);
+    uint64_t em = __ballot(k == 0);
+    if (lane == 0) {
+        child[node * b.W + w] = cm;
+        value[node * b.W + w] = vm;
+        rank[node * b.W + w] = (uint32_t)leaf_idx[r * b.n_slot + (int64_t)w * 64];
+        atomicAdd((unsigned long long *)&counts->n_tiles_full, (unsigned long long)__popcll(vm));
+        atomicAdd((unsigned long long *)&counts->n_tiles_empty, (unsigned long long)__popcll(em));
+    }
+}
+
+__global__ void leaf_write_kernel(BuildDims b, const int32_t *__restrict__ mixed, const int64_t *__restrict__ leaf_idx,
+                                  const uint64_t *__restrict__ masks, uint64_t *__restrict__ leaves,
+                                  VdbCounts *counts) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t e = t >> 3;
+    int j = (int)(t & 7);
+    if (e >= b.n_block) return;
+    if (e == 0 && j == 0) counts->n_leaves = leaf_idx[b.n_block];
+    if (!mixed[e]) return;
+    leaves[leaf_idx[e] * 8 + j] = masks[e * 8 + j];
+}
+
+// decode a VDB tree into dense bytes, one thread per voxel
+__global__ void vdb_unpack_kernel(GridView g, uint8_t *__restrict__ out) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t R = (uint64_t)g.R;
+    if (i >= (uint64_t)g.L * R * R * R) return;
+    int z = (int)(i % R), y = (int)((i / R) % R), x = (int)((i / (R * R)) % R), lev = (int)(i / (R * R * R));
+    const int sh = 3 + g.ilog2;
+    int ri = ((lev * g.NR + (x >> sh)) * g.NR + (y >> sh)) * g.NR + (z >> sh);
+    int node = g.root[ri];
+    uint8_t v;
+    if (node < 0) {
+        v = node == -2;
+    } else {
+        const int m = g.S - 1;
+        int s = (((x >> 3) & m) * g.S + ((y >> 3) & m)) * g.S + ((z >> 3) & m);
+        int w = node * g.W + (s >> 6);
+        uint64_t bit = 1ull << (s & 63);
+        if (g.child[w] & bit) {
+            uint32_t li = g.rank[w] + (uint32_t)__popcll(g.child[w] & (bit - 1));
+            v = (g.leaves[(uint64_t)li * 8 + (x & 7)] >> (((y & 7) << 3) | (z & 7))) & 1ull;
+        } else {
+            v = (g.value[w] & bit) != 0;
+        }
+    }
+    out[i] = v;
+}
+
+__global__ void zero_counts_kernel(VdbCounts *c) {
+    if (threadIdx.x == 0) *c = VdbCounts{0, 0, 0, 0, 0, 0};
+}
+
+ogv_status check_common(int32_t L, int32_t R, const float *boxes, const uint8_t *occ, ogv_grid **out) {
+    if (!out) OGV_FAIL(OGV_ERR_INVALID, "out is null");
+    *out = nullptr;
+    if (L < 1 || L > kMaxLevels) OGV_FAIL(OGV_ERR_INVALID, "n_levels must be in 1..8");
+    if (R < 1 || R > OGV_MAX_RES) OGV_FAIL(OGV_ERR_INVALID, "res must be in 1..1024");
+    if (!boxes || !occ) OGV_FAIL(OGV_ERR_INVALID, "null boxes or occupancy");
+    std::string why;
+    if (!boxes_valid(L, R, boxes, &why)) OGV_FAIL(OGV_ERR_INVALID, why);
+    return OGV_OK;
+}
+
+}  // namespace
+}  // namespace ogv
+
+using namespace ogv;
+
+extern "C" const char *ogv_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *ogv_version(void) { return "ogvdb 0.1 (gfx950)"; }
+
+extern "C" ogv_status ogv_dense_build(int32_t L, int32_t R, const float *boxes, const uint8_t *occ, ogv_grid **out,
+                                      void *stream) {
+    ogv_status st = check_common(L, R, boxes, occ, out);
+    if (st != OGV_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    uint64_t n_vox = (uint64_t)L * R * R * R;
+    uint64_t n_words = (n_vox + 31) / 32;
+    size_t off_boxes = 0, off_bits = 256;
+    size_t total = off_bits + n_words * 4;
+    ogv_grid *g = new ogv_grid();
+    if (hipMalloc(&g->mem, total) != hipSuccess) {
+        delete g;
+        OGV_FAIL(OGV_ERR_OOM, "device allocation of " + std::to_string(total) + " bytes failed");
+    }
+    g->mem_bytes = total;
+    g->used_bytes = n_words * 4;
+    std::memcpy(g->boxes_host, boxes, sizeof(float) * 6 * L);
+    g->build_stream = s;
+    GridView &v = g->view;
+    std::memset(&v, 0, sizeof(v));
+    v.kind = 0;
+    v.L = L;
+    v.R = R;
+    v.boxes = (const float *)((char *)g->mem + off_boxes);
+    v.bits = (const uint32_t *)((char *)g->mem + off_bits);
+    hipError_t e = hipMemcpyAsync((void *)v.boxes, g->boxes_host, sizeof(float) * 6 * L, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        dense_pack_kernel<<<(unsigned)((n_words + 255) / 256), 256, 0, s>>>(occ, n_vox, (uint32_t *)v.bits, n_words);
+        e = hipGetLastError();
+    }
+    // the host copy of the boxes must outlive the async copy
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(g->mem);
+        delete g;
+        OGV_FAIL(OGV_ERR_HIP, std::string("dense build failed: ") + hipGetErrorString(e));
+    }
+    g->counts_ready = true;
+    *out = g;
+    return OGV_OK;
+}
+
+extern "C" ogv_status ogv_vdb_build(int32_t L, int32_t R, const float *boxes, const uint8_t *occ, int32_t ilog2,
+                                    ogv_grid **out, void *stream) {
+    ogv_status st = check_common(L, R, boxes, occ, out);
+    if (st != OGV_OK) return st;
+    if (ilog2 < 1 || ilog2 > 5) OGV_FAIL(OGV_ERR_INVALID, "internal_log2 must be in 1..5");
+    hipStream_t s = (hipStream_t)stream;
+    BuildDims b;
+    b.L = L;
+    b.R = R;
+    b.ilog2 = ilog2;
+    b.S = 1 << ilog2;
+    b.D = 8 * b.S;
+    b.NR = (R + b.D - 1) / b.D;
+    b.n_root = (int64_t)L * b.NR * b.NR * b.NR;
+    b.n_slot = (int64_t)b.S * b.S * b.S;
+    b.n_block = b.n_root * b.n_slot;
+    b.W = (int)((b.n_slot + 63) / 64);
+
+    // final storage, sized for the worst case (every root a node, every
+    // block a leaf); the occupied part is reported by ogv_grid_info_get
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    size_t o_boxes = take(sizeof(float) * 6 * L);
+    size_t o_counts = take(sizeof(VdbCounts));
+    size_t o_root = take(sizeof(int32_t) * b.n_root);
+    size_t o_child = take(sizeof(uint64_t) * b.n_root * b.W);
+    size_t o_value = take(sizeof(uint64_t) * b.n_root * b.W);
+    size_t o_rank = take(sizeof(uint32_t) * b.n_root * b.W);
+    size_t o_leaves = take(sizeof(uint64_t) * 8 * b.n_block);
+    size_t total = off;
+    // build scratch
+    off = 0;
+    size_t t_kind = take(sizeof(int32_t) * b.n_block);
+    size_t t_mixed = take(sizeof(int32_t) * b.n_block);
+    size_t t_masks = take(sizeof(uint64_t) * 8 * b.n_block);
+    size_t t_leafidx = take(sizeof(int64_t) * (b.n_block + 1));
+    size_t t_rootkind = take(sizeof(int32_t) * b.n_root);
+    size_t t_isnode = take(sizeof(int32_t) * b.n_root);
+    size_t t_nodeidx = take(sizeof(int64_t) * (b.n_root + 1));
+    size_t t_tiles = take(sizeof(int64_t) * (scan_tiles(b.n_block) + 1));
+    size_t scratch_total = off;
+
+    ogv_grid *g = new ogv_grid();
+    void *scratch = nullptr;
+    if (hipMalloc(&g->mem, total) != hipSuccess) {
+        delete g;
+        OGV_FAIL(OGV_ERR_OOM, "device allocation of " + std::to_string(total) + " bytes failed");
+    }
+    if (hipMalloc(&scratch, scratch_total) != hipSuccess) {
+        (void)hipFree(g->mem);
+        delete g;
+        OGV_FAIL(OGV_ERR_OOM, "device allocation of " + std::to_string(scratch_total) + " bytes failed");
+    }
+    g->mem_bytes = total;
+    std::memcpy(g->boxes_host, boxes, sizeof(float) * 6 * L);
+    g->build_stream = s;
+    char *m = (char *)g->mem, *t = (char *)scratch;
+    GridView &v = g->view;
+    std::memset(&v, 0, sizeof(v));
+    v.kind = 1;
+    v.L = L;
+    v.R = R;
+    v.ilog2 = ilog2;
+    v.S = b.S;
+    v.NR = b.NR;
+    v.W = b.W;
+    v.boxes = (const float *)(m + o_boxes);
+    v.root = (const int32_t *)(m + o_root);
+    v.child = (const uint64_t *)(m + o_child);
+    v.value = (const uint64_t *)(m + o_value);
+    v.rank = (const uint32_t *)(m + o_rank);
+    v.leaves = (const uint64_t *)(m + o_leaves);
+    g->counts_dev = (VdbCounts *)(m + o_counts);
+
+    int32_t *kind = (int32_t *)(t + t_kind), *mixed = (int32_t *)(t + t_mixed);
+    uint64_t *masks = (uint64_t *)(t + t_masks);
+    int64_t *leaf_idx = (int64_t *)(t + t_leafidx), *node_idx = (int64_t *)(t + t_nodeidx);
+    int32_t *root_kind = (int32_t *)(t + t_rootkind), *is_node = (int32_t *)(t + t_isnode);
+    int64_t *tiles = (int64_t *)(t + t_tiles);
+
+    hipError_t e = hipMemcpyAsync((void *)v.boxes, g->boxes_host, sizeof(float) * 6 * L, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        zero_counts_kernel<<<1, 64, 0, s>>>(g->counts_dev);
+        classify_kernel<<<(unsigned)((b.n_block + 3) / 4), 256, 0, s>>>(b, occ, kind, mixed, masks);
+        root_kernel<<<(unsigned)b.n_root, 256, 0, s>>>(b, kind, root_kind, is_node);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = launch_excl_scan(is_node, b.n_root, node_idx, tiles, 0, nullptr, s);
+    if (e == hipSuccess) {
+        root_write_kernel<<<(unsigned)((b.n_root + 255) / 256), 256, 0, s>>>(b, root_kind, node_idx,
+                                                                            (int32_t *)v.root, g->counts_dev);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = launch_excl_scan(mixed, b.n_block, leaf_idx, tiles, 0, nullptr, s);
+    if (e == hipSuccess) {
+        node_write_kernel<<<(unsigned)((b.n_root * b.W + 3) / 4), 256, 0, s>>>(
+            b, root_kind, node_idx, kind, leaf_idx, (uint64_t *)v.child, (uint64_t *)v.value, (uint32_t *)v.rank,
+            g->counts_dev);
+        leaf_write_kernel<<<(unsigned)((b.n_block * 8 + 255) / 256), 256, 0, s>>>(b, mixed, leaf_idx, masks,
+                                                                                 (uint64_t *)v.leaves, g->counts_dev);
+        e = hipGetLastError();
+    }
+    // scratch is released once the build has run; this also keeps the host
+    // copy of the boxes alive long enough for the async copy
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(scratch);
+    if (e != hipSuccess) {
+        (void)hipFree(g->mem);
+        delete g;
+        OGV_FAIL(OGV_ERR_HIP, std::string("VDB build failed: ") + hipGetErrorString(e));
+    }
+    *out = g;
+    return OGV_OK;
+}
+
+extern "C" ogv_status ogv_grid_info_get(const ogv_grid *grid, ogv_grid_info *info) {
+    if (!grid || !info) OGV_FAIL(OGV_ERR_INVALID, "null argument");
+    ogv_grid *g = const_cast<ogv_grid *>(grid);
+    const GridView &v = g->view;
+    std::memset(info, 0, sizeof(*info));
+    info->kind = v.kind;
+    info->n_levels = v.L;
+    info->res = v.R;
+    info->internal_log2 = v.ilog2;
+    if (v.kind == 0) {
+        info->bytes = (int64_t)g->used_bytes;
+        return OGV_OK;
+    }
+    if (!g->counts_ready) {
+        OGV_CHECK_HIP(hipStreamSynchronize(g->build_stream));
+        OGV_CHECK_HIP(hipMemcpy(&g->counts_host, g->counts_dev, sizeof(VdbCounts), hipMemcpyDeviceToHost));
+        g->counts_ready = true;
+        const int64_t n_root = (int64_t)v.L * v.NR * v.NR * v.NR;
+        g->used_bytes = (size_t)(n_root * 4 + g->counts_host.n_nodes * (int64_t)v.W * (8 + 8 + 4) +
+                                 g->counts_host.n_leaves * 64);
+    }
+    const VdbCounts &c = g->counts_host;
+    info->bytes = (int64_t)g->used_bytes;
+    info->n_nodes = c.n_nodes;
+    info->n_leaves = c.n_leaves;
+    info->n_tiles_full = c.n_tiles_full;
+    info->n_tiles_empty = c.n_tiles_empty;
+    info->n_root_tiles_full = c.n_root_full;
+    info->n_root_tiles_empty = c.n_root_empty;
+    return OGV_OK;
+}
+
+extern "C" ogv_status ogv_grid_to_dense(const ogv_grid *grid, uint8_t *out, void *stream) {
+    if (!grid || !out) OGV_FAIL(OGV_ERR_INVALID, "null argument");
+    const GridView &v = grid->view;
+    uint64_t n_vox = (uint64_t)v.L * v.R * v.R * v.R;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned blocks = (unsigned)((n_vox + 255) / 256);
+    if (v.kind == 0) dense_unpack_kernel<<<blocks, 256, 0, s>>>(v.bits, n_vox, out);
+    else vdb_unpack_kernel<<<blocks, 256, 0, s>>>(v, out);
+    OGV_CHECK_LAUNCH();
+    return OGV_OK;
+}
+
+extern "C" void ogv_grid_destroy(ogv_grid *grid) {
+    if (!grid) return;
+    (void)hipFree(grid->mem);
+    delete grid;
+}

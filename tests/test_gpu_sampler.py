@@ -1,0 +1,263 @@
+"""GPU sampler parity: the HIP kernels against the CPU oracle, element by element.
+
+The bar (sample-exact): identical per-ray counts (offsets), ray ids and voxel
+ids, and t0/t1 within 1e-5 absolute in binary32 -- asserted here as bit-exact,
+which the shared binary32 definition makes reachable.  Every case runs the
+dense voxel DDA and VDB + hierarchical DDA, each as Alg. 1 (branch) and
+Alg. 2 (skip).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2404_10272_amd import api, scenes
+from tests import handmade
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [("dense", "branch"), ("dense", "skip"), ("vdb", "branch"), ("vdb", "skip")]
+_VID = lambda v: f"{v[0]}-{v[1]}"
+
+
+def gpu_grid(kind, occ, boxes, ilog2):
+    occ_d = torch.from_numpy(np.ascontiguousarray(occ)).cuda()
+    if kind == "dense":
+        return api.build_dense(occ_d, boxes)
+    return api.build_vdb(occ_d, boxes, ilog2)
+
+
+def gpu_sample(grid, o, d, near, far, step, variant, voxel_ids=True):
+    out = api.sample_rays(grid, torch.from_numpy(np.ascontiguousarray(o)).cuda(),
+                          torch.from_numpy(np.ascontiguousarray(d)).cuda(), near, far, api.make_step(step),
+                          variant, voxel_ids=voxel_ids)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def assert_same(got, ref, what=""):
+    np.testing.assert_array_equal(got["offsets"], ref["offsets"], err_msg=f"{what} offsets")
+    for k in ["ray_ids", "voxel_ids"]:
+        if k in got:
+            np.testing.assert_array_equal(got[k], ref[k], err_msg=f"{what} {k}")
+    for k in ["t0", "t1"]:
+        assert np.max(np.abs(got[k].astype(np.float64) - ref[k]), initial=0.0) <= 1e-5, f"{what} {k}"
+        np.testing.assert_array_equal(got[k], ref[k], err_msg=f"{what} {k} (bit-exact)")
+
+
+# ------------------------------------------------------------------ hand-made
+
+@pytest.mark.parametrize("variant", VARIANTS, ids=_VID)
+def test_handmade_cases(variant):
+    for case in handmade.load()["cases"]:
+        occ, boxes = handmade.grid_of(case)
+        for ilog2 in (1, 3):
+            g = gpu_grid(variant[0], occ, boxes, ilog2)
+            o = np.asarray([case["o"]], np.float32)
+            d = np.asarray([case["d"]], np.float32)
+            got = gpu_sample(g, o, d, case["tmin"], case["tmax"], handmade.step_of(case), variant[1])
+            print(case["name"], variant, ilog2, flush=True)
+            np.testing.assert_array_equal(got["t0"], np.asarray(case["t0"], np.float32), err_msg=case["name"])
+            np.testing.assert_array_equal(got["t1"], np.asarray(case["t1"], np.float32), err_msg=case["name"])
+            np.testing.assert_array_equal(got["voxel_ids"], np.asarray(case["vox"], np.int32), err_msg=case["name"])
+
+
+def test_handmade_vdb_structure():
+    data = handmade.load()
+    cases = [c for c in data["cases"] if "vdb" in c] + data["vdb_cases"]
+    for case in cases:
+        occ, boxes = handmade.grid_of(case)
+        want = case.get("stats") or {k: v for k, v in case["vdb"].items() if k != "ilog2"}
+        ilog2 = case.get("ilog2", case.get("vdb", {}).get("ilog2"))
+        info = gpu_grid("vdb", occ, boxes, ilog2).info()
+        got = {"nodes": info["n_nodes"], "leaves": info["n_leaves"], "slot_full": info["n_tiles_full"],
+               "slot_empty": info["n_tiles_empty"], "root_full": info["n_root_tiles_full"],
+               "root_empty": info["n_root_tiles_empty"]}
+        assert got == want, case["name"]
+
+
+# ------------------------------------------------------------------ random tiny grids, edge rays
+
+def edge_rays(rng, R, L, n):
+    """Rays of every awkward kind: free, axis-aligned (on planes), diagonal
+    (edge/corner ties), origin inside, zero / -0 / denormal components."""
+    span = 2.0 ** (L - 1)
+    h = 2.0 / R
+    o = rng.uniform(-3 * span, 3 * span, (n, 3))
+    d = rng.uniform(-span, span, (n, 3)) - o
+    kind = rng.integers(0, 6, n)
+    for i in range(n):
+        if kind[i] == 1:
+            a = rng.integers(3)
+            d[i] = 0
+            d[i, a] = rng.choice([-1.0, 1.0])
+            o[i] = np.round(rng.uniform(-span, span, 3) / h * 2) * h / 2
+            o[i, a] = -d[i, a] * 3 * span
+        elif kind[i] == 2:
+            d[i] = rng.choice([-1.0, 1.0], 3) * rng.choice([0.0, 1.0, 1.0], 3)
+            if not d[i].any():
+                d[i, 0] = 1.0
+            o[i] = -d[i] * 3 * span + np.round(rng.uniform(-span, span, 3) / h) * h * (d[i] == 0)
+        elif kind[i] == 3:
+            o[i] = rng.uniform(-span, span, 3)
+    nrm = np.linalg.norm(d, axis=1, keepdims=True)
+    d = d / np.where(nrm > 0, nrm, 1.0)
+    specials = [0.0, -0.0, 1e-45, -1e-40, 3e-39]
+    for i in np.nonzero(kind == 4)[0]:
+        d[i, rng.integers(3)] = specials[rng.integers(len(specials))]
+    return o.astype(np.float32), d.astype(np.float32)
+
+
+STEPS = [oracle.make_step("const", dt=0.0625), oracle.make_step("const", dt=0.037),
+         oracle.make_step("cone", cone=1 / 16, dt_min=0.02)]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_tiny_grids(seed):
+    rng = np.random.default_rng(seed)
+    R = [4, 8, 12, 16, 24, 40][seed]
+    L = 1 + seed % 3
+    boxes = np.asarray([[-2.0 ** l] * 3 + [2.0 ** l] * 3 for l in range(L)], np.float32)
+    occ = (rng.random((L, R, R, R)) < [0.05, 0.3, 0.6][seed % 3]).astype(np.uint8)
+    if seed == 5:
+        occ[:, :8, :8, :8] = 1   # full blocks -> tiles
+        occ[:, 16:32, 16:32, 16:32] = 0
+    o, d = edge_rays(rng, R, L, 3000)
+    o[7] = [np.nan, 0, 0]
+    d[8] = [0, np.inf, 0]
+    scene = oracle.Scene(occ, boxes)
+    for step in STEPS:
+        for tmin, tmax in [(0.0, 30.0), (1.5, 4.0), (3.0, 2.0)]:
+            ref = oracle.sample_rays(scene, o, d, tmin, tmax, step, "brute")
+            for variant in VARIANTS:
+                for ilog2 in (1, 2):
+                    if variant[0] == "dense" and ilog2 == 2:
+                        continue
+                    g = gpu_grid(variant[0], occ, boxes, ilog2)
+                    got = gpu_sample(g, o, d, tmin, tmax, step, variant[1])
+                    assert_same(got, ref, f"seed{seed} {variant} {step} {tmin},{tmax} ilog2={ilog2}")
+
+
+# ------------------------------------------------------------------ workloads
+
+def _oracle_all(w, method="dense_branch", sub=slice(None)):
+    scene = oracle.Scene(w.occ, w.boxes)
+    return oracle.sample_rays(scene, w.origins[sub], w.dirs[sub], w.near, w.far, w.step, method, ilog2=w.ilog2)
+
+
+@pytest.fixture(scope="module")
+def small():
+    return scenes.workload("small")
+
+
+@pytest.fixture(scope="module")
+def small_ref(small):
+    return _oracle_all(small, "brute")
+
+
+@pytest.mark.parametrize("variant", VARIANTS, ids=_VID)
+def test_small_workload_all_rays(small, small_ref, variant):
+    g = gpu_grid(variant[0], small.occ, small.boxes, small.ilog2)
+    got = gpu_sample(g, small.origins, small.dirs, small.near, small.far, small.step, variant[1])
+    assert_same(got, small_ref, f"small {variant}")
+
+
+@pytest.fixture(scope="module")
+def obj():
+    return scenes.workload("object")
+
+
+@pytest.fixture(scope="module")
+def obj_ref(obj):
+    return _oracle_all(obj)
+
+
+@pytest.mark.parametrize("variant", VARIANTS, ids=_VID)
+def test_object_workload_800x800(obj, obj_ref, variant):
+    """Full 640,000-ray object-scene workload, with voxel ids (debug kernels)
+    and without (the kernels the benchmark times)."""
+    g = gpu_grid(variant[0], obj.occ, obj.boxes, obj.ilog2)
+    got = gpu_sample(g, obj.origins, obj.dirs, obj.near, obj.far, obj.step, variant[1], voxel_ids=True)
+    assert_same(got, obj_ref, f"object {variant}")
+    got = gpu_sample(g, obj.origins, obj.dirs, obj.near, obj.far, obj.step, variant[1], voxel_ids=False)
+    assert_same(got, obj_ref, f"object {variant} (no voxel ids)")
+
+
+def test_object_workload_capacity_mode(obj, obj_ref):
+    """The one-call capacity path the benchmark times: exact capacity, then a
+    too-small capacity (overflow flagged, nothing written past it)."""
+    g = gpu_grid("vdb", obj.occ, obj.boxes, obj.ilog2)
+    o = torch.from_numpy(obj.origins).cuda()
+    d = torch.from_numpy(obj.dirs).cuda()
+    S = int(obj_ref["offsets"][-1])
+    sp = api.Sampler(g, obj.n_rays, obj.near, obj.far, obj.step, "skip")
+    for cap in (S, S // 3):
+        ids = torch.full((cap + 16,), -7, dtype=torch.int32, device="cuda")
+        t0 = torch.zeros(cap + 16, device="cuda")
+        t1 = torch.zeros(cap + 16, device="cuda")
+        offsets, overflow = sp.rays(o, d, ids[:cap], t0[:cap], t1[:cap])
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(offsets.cpu().numpy(), obj_ref["offsets"])
+        assert int(overflow.item()) == (1 if cap < S else 0)
+        np.testing.assert_array_equal(t0[:cap].cpu().numpy(), obj_ref["t0"][:cap])
+        np.testing.assert_array_equal(ids[:cap].cpu().numpy(), obj_ref["ray_ids"][:cap])
+        assert bool((ids[cap:] == -7).all())
+
+
+@pytest.fixture(scope="module")
+def unb():
+    return scenes.workload("unbounded")
+
+
+@pytest.mark.parametrize("variant", VARIANTS, ids=_VID)
+def test_unbounded_cascades(unb, variant):
+    """4 nested cascades, growing step: all 1,064,960 rays."""
+    ref = _oracle_all(unb, "dense_branch")
+    g = gpu_grid(variant[0], unb.occ, unb.boxes, unb.ilog2)
+    got = gpu_sample(g, unb.origins, unb.dirs, unb.near, unb.far, unb.step, variant[1], voxel_ids=True)
+    assert_same(got, ref, f"unbounded {variant}")
+
+
+# ------------------------------------------------------------------ structure, edges, errors
+
+@pytest.mark.parametrize("name", ["small", "object", "unbounded"])
+def test_vdb_round_trip_and_counts(name):
+    w = scenes.workload(name)
+    g = gpu_grid("vdb", w.occ, w.boxes, w.ilog2)
+    np.testing.assert_array_equal(g.to_dense().cpu().numpy(), w.occ)
+    info = g.info()
+    st = oracle.Scene(w.occ, w.boxes).vdb_stats(w.ilog2)
+    assert (info["n_nodes"], info["n_leaves"], info["n_tiles_full"], info["n_tiles_empty"],
+            info["n_root_tiles_full"], info["n_root_tiles_empty"]) == (
+        st["nodes"], st["leaves"], st["slot_full"], st["slot_empty"], st["root_full"], st["root_empty"])
+    d = gpu_grid("dense", w.occ, w.boxes, w.ilog2)
+    np.testing.assert_array_equal(d.to_dense().cpu().numpy(), w.occ)
+    assert d.info()["bytes"] == w.occ.size // 8
+
+
+def test_empty_batch_and_far_before_near(small):
+    g = gpu_grid("vdb", small.occ, small.boxes, small.ilog2)
+    e = np.zeros((0, 3), np.float32)
+    got = gpu_sample(g, e, e, small.near, small.far, small.step, "skip")
+    assert got["offsets"].tolist() == [0] and got["t0"].size == 0
+    got = gpu_sample(g, small.origins, small.dirs, 6.0, 2.0, small.step, "skip")
+    assert got["offsets"][-1] == 0
+
+
+def test_invalid_arguments_raise(small):
+    g = gpu_grid("vdb", small.occ, small.boxes, small.ilog2)
+    o = torch.from_numpy(small.origins).cuda()
+    with pytest.raises(api.OgvError):
+        api.sample_rays(g, o, o, float("nan"), 6.0, api.make_step(small.step))
+    with pytest.raises(api.OgvError):
+        api.sample_rays(g, o, o, 2.0, 6.0, api.make_step("const", dt=0.0))
+    with pytest.raises(api.OgvError):
+        api.build_vdb(torch.zeros((8, 8, 8), dtype=torch.uint8, device="cuda"), [0, 0, 0, 1, 1, 1], internal_log2=9)
+
+
+def test_determinism(obj):
+    g = gpu_grid("vdb", obj.occ, obj.boxes, obj.ilog2)
+    a = gpu_sample(g, obj.origins, obj.dirs, obj.near, obj.far, obj.step, "skip", voxel_ids=False)
+    b = gpu_sample(g, obj.origins, obj.dirs, obj.near, obj.far, obj.step, "skip", voxel_ids=False)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k

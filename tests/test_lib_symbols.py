@@ -1,0 +1,55 @@
+"""The C-ABI library loads without a GPU and exports every function include/ogvdb.h declares."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ogvdb.h")
+LIB = os.path.join(ROOT, "paper_2404_10272_amd", "libogvdb.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ogv_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_sampler_boundary():
+    names = declared()
+    for n in ["ogv_vdb_build", "ogv_dense_build", "ogv_sample_count", "ogv_sample_fill", "ogv_sample_rays",
+              "ogv_composite_fwd", "ogv_composite_bwd", "ogv_last_error"]:
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_signatures_cover_header():
+    from paper_2404_10272_amd import api
+    assert set(declared()) <= set(api.SIGNATURES), set(declared()) - set(api.SIGNATURES)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_host_side_validation_without_gpu():
+    # argument checks run before any device work, so they answer on a CPU host
+    from paper_2404_10272_amd import api
+    L = api.lib()
+    n = ctypes.c_size_t()
+    bad = api.make_step("cone", cone=1 / 256, dt_min=1e-3)
+    assert L.ogv_sample_workspace_size(-1, 0.0, 1.0, ctypes.byref(bad), ctypes.byref(n)) == -1
+    assert L.ogv_sample_workspace_size(100, 0.05, 1000.0, ctypes.byref(bad), ctypes.byref(n)) == 0
+    assert n.value > 100 * 4
+    h = ctypes.c_void_p()
+    boxes = (ctypes.c_float * 6)(0, 0, 0, 1, 1, 1)
+    assert L.ogv_vdb_build(1, 0, boxes, ctypes.c_void_p(1), 4, ctypes.byref(h), None) == -1
+    assert b"res" in L.ogv_last_error()
+    nested_wrong = (ctypes.c_float * 12)(-2, -2, -2, 2, 2, 2, -1, -1, -1, 1, 1, 1)
+    assert L.ogv_dense_build(2, 8, nested_wrong, ctypes.c_void_p(1), ctypes.byref(h), None) == -1
+    assert b"contain" in L.ogv_last_error()
