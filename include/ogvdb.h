@@ -138,6 +138,9 @@ ogv_status ogv_sample_count(const ogv_grid *grid, int32_t variant, const float *
 
 /* Emission pass: writes ray i's samples at offsets[i] .. offsets[i+1]-1.
  *   offsets_dev       from ogv_sample_count with the same arguments.
+ *   ws_dev            the workspace that ogv_sample_count filled, unchanged
+ *                     since: it holds each ray's occupied runs (and the
+ *                     growing-step table), which this pass expands.
  *   capacity          length of the sample arrays; samples at index >=
  *                     capacity are not written.
  *   ray_ids_dev int32 [capacity], t0_dev/t1_dev float32 [capacity].
@@ -175,6 +178,59 @@ ogv_status ogv_composite_fwd(const int64_t *offsets_dev, int64_t n_rays, const f
 ogv_status ogv_composite_bwd(const int64_t *offsets_dev, int64_t n_rays, const float *t0_dev, const float *t1_dev,
                              const float *sigma_dev, const float *rgb_dev, const float *g_rgb_dev,
                              const float *g_opacity_dev, float *d_sigma_dev, float *d_rgb_dev, void *stream);
+
+/* ---------------------------------------------------------------- batches
+ * Many scenes, uneven grids and ray counts, in one graph-captured pass: a
+ * persistent counting kernel pulls chunks of rays from a queue that spans
+ * all scenes, one scan numbers every sample, and one expansion kernel
+ * writes them.  Not in the paper (it renders one scene at a time); the
+ * per-ray result is exactly ogv_sample_rays's. */
+typedef struct {
+    const ogv_grid *grid;                /* dense or VDB, built on this device */
+    const float *origins_dev, *dirs_dev; /* float32 [n_rays][3] */
+    int64_t n_rays;
+    float near_t, far_t;
+    ogv_step step;
+} ogv_scene;
+
+typedef struct {
+    int32_t chunk;          /* rays per queue item, a multiple of 256 */
+    int32_t blocks_per_cu;  /* persistent workgroups (256 threads) per compute unit */
+} ogv_tune;
+
+typedef struct ogv_batch ogv_batch;
+
+typedef struct {
+    int64_t n_rays;         /* all scenes' rays; scene s starts at ray_base[s] */
+    int32_t n_scenes;
+    ogv_tune tune;          /* the choice in use */
+    int32_t tuned;          /* 1 if chosen by the autotuner */
+    float tune_ms;          /* counting time of the chosen tune when tuned */
+} ogv_batch_info;
+
+/* Plans a batched pass over scenes_host[0..n_scenes-1] (1..64 scenes; the
+ * descriptors are copied, the grids and ray buffers must stay alive and
+ * unchanged while the batch is used).  tune_host NULL runs the autotuner:
+ * every candidate queue chunk and persistent grid size is timed on `stream`
+ * (this synchronizes) and the fastest kept.  The batch owns its workspace. */
+ogv_status ogv_batch_create(const ogv_scene *scenes_host, int32_t n_scenes, int32_t variant,
+                            const ogv_tune *tune_host, ogv_batch **out, void *stream);
+
+ogv_status ogv_batch_info_get(const ogv_batch *batch, ogv_batch_info *info_host, int64_t *ray_base_host);
+
+/* One pass, replayed from a captured HIP graph (captured on first use and
+ * again whenever the output pointers or capacity change).  Outputs form one
+ * CSR over the scenes' rays concatenated in scene order: offsets_dev int64
+ * [n_rays + 1]; ray_ids are global ray indices (scene s, ray i ->
+ * ray_base[s] + i); capacity and overflow_dev as in ogv_sample_rays. */
+ogv_status ogv_batch_launch(ogv_batch *batch, int64_t *offsets_dev, int64_t capacity, int32_t *ray_ids_dev,
+                            float *t0_dev, float *t1_dev, int32_t *overflow_dev, void *stream);
+
+/* The same pass as plain kernel launches, no graph (for comparison). */
+ogv_status ogv_batch_launch_eager(ogv_batch *batch, int64_t *offsets_dev, int64_t capacity, int32_t *ray_ids_dev,
+                                  float *t0_dev, float *t1_dev, int32_t *overflow_dev, void *stream);
+
+void ogv_batch_destroy(ogv_batch *batch);
 
 /* Message for the last non-OK status returned on the calling thread. */
 const char *ogv_last_error(void);

@@ -33,6 +33,20 @@ class _Info(ctypes.Structure):
                 ("n_root_tiles_full", ctypes.c_int64), ("n_root_tiles_empty", ctypes.c_int64)]
 
 
+class _Scene(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_void_p), ("origins", ctypes.c_void_p), ("dirs", ctypes.c_void_p),
+                ("n_rays", ctypes.c_int64), ("near_t", ctypes.c_float), ("far_t", ctypes.c_float), ("step", _Step)]
+
+
+class _Tune(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+
+
+class _BatchInfo(ctypes.Structure):
+    _fields_ = [("n_rays", ctypes.c_int64), ("n_scenes", ctypes.c_int32), ("tune", _Tune), ("tuned", ctypes.c_int32),
+                ("tune_ms", ctypes.c_float)]
+
+
 _lib = None
 VP, I32, I64, F32, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
 
@@ -51,6 +65,11 @@ SIGNATURES = {
                               VP, SZ, VP]),
     "ogv_composite_fwd": (I32, [VP, I64, VP, VP, VP, VP, VP, VP, VP]),
     "ogv_composite_bwd": (I32, [VP, I64, VP, VP, VP, VP, VP, VP, VP, VP, VP]),
+    "ogv_batch_create": (I32, [ctypes.POINTER(_Scene), I32, I32, ctypes.POINTER(_Tune), ctypes.POINTER(VP), VP]),
+    "ogv_batch_info_get": (I32, [VP, ctypes.POINTER(_BatchInfo), VP]),
+    "ogv_batch_launch": (I32, [VP, VP, I64, VP, VP, VP, VP, VP]),
+    "ogv_batch_launch_eager": (I32, [VP, VP, I64, VP, VP, VP, VP, VP]),
+    "ogv_batch_destroy": (None, [VP]),
     "ogv_last_error": (ctypes.c_char_p, []),
     "ogv_version": (ctypes.c_char_p, []),
 }
@@ -232,6 +251,60 @@ def sample_rays(grid, origins, dirs, near, far, step, variant="skip", voxel_ids=
     if voxel_ids:
         out["voxel_ids"] = vox
     return out
+
+
+# ---------------------------------------------------------------- batches
+
+class Batch:
+    """Many scenes sampled in one graph-captured pass (see ogv_batch_create).
+
+    scenes: list of (grid, origins, dirs, near, far, step).  tune: None to
+    autotune, or (chunk, blocks_per_cu).  The grids and ray tensors are kept
+    alive by this object.
+    """
+
+    def __init__(self, scenes, variant="skip", tune=None, stream=None):
+        self._keep = []
+        arr = (_Scene * len(scenes))()
+        for i, (grid, o, d, near, far, step) in enumerate(scenes):
+            o, d, n = _rays(o, d)
+            self._keep += [grid, o, d]
+            st = step if isinstance(step, _Step) else make_step(step)
+            arr[i] = _Scene(grid.handle, o.data_ptr(), d.data_ptr(), n, float(near), float(far), st)
+        t = None if tune is None else ctypes.byref(_Tune(int(tune[0]), int(tune[1])))
+        h = ctypes.c_void_p()
+        _check(lib().ogv_batch_create(arr, len(scenes), _variant(variant), t, ctypes.byref(h), _stream(stream)))
+        self._h = h
+        self.n_scenes = len(scenes)
+        info = self.info()
+        self.n_rays = info["n_rays"]
+        self.offsets = torch.empty(self.n_rays + 1, dtype=torch.int64, device="cuda")
+        self.overflow = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def info(self):
+        inf = _BatchInfo()
+        base = (ctypes.c_int64 * self.n_scenes)()
+        _check(lib().ogv_batch_info_get(self._h, ctypes.byref(inf), base))
+        return {"n_rays": inf.n_rays, "n_scenes": inf.n_scenes, "chunk": inf.tune.chunk,
+                "blocks_per_cu": inf.tune.blocks_per_cu, "tuned": bool(inf.tuned), "tune_ms": inf.tune_ms,
+                "ray_base": list(base)}
+
+    def launch(self, ray_ids, t0, t1, graph=True, stream=None):
+        fn = lib().ogv_batch_launch if graph else lib().ogv_batch_launch_eager
+        _check(fn(self._h, _ptr(self.offsets), int(t0.numel()), _ptr(ray_ids), _ptr(t0), _ptr(t1),
+                  _ptr(self.overflow), _stream(stream)))
+        return self.offsets, self.overflow
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ogv_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------- composite

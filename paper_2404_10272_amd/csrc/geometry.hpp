@@ -86,17 +86,21 @@ struct Axis {
     }
 };
 
-__device__ __forceinline__ Axis make_axis(const float *box, int a, int R, float o, float d) {
+// Axis a of level `lev`: plane geometry from the per-level table written at
+// build time (B, h = fl((A-B)/R), approximate 1/h), ray origin/direction
+// component and its correctly rounded reciprocal r = fl(1/d).
+__device__ __forceinline__ Axis load_axis(const float *geom, int lev, int a, int R, float o, float d, float r) {
+    const float *G = geom + 12 * lev;
     Axis x;
-    x.B = box[a];
-    x.h = __fdiv_rn(__fsub_rn(box[3 + a], box[a]), (float)R);
-    x.inv_h = (float)R / (box[3 + a] - box[a]);
+    x.B = G[a];
+    x.h = G[3 + a];
+    x.inv_h = G[6 + a];
     x.o = o;
     x.d = d;
-    x.r = __fdiv_rn(1.0f, d);
+    x.r = r;
     x.R = R;
     x.pos = d > 0.0f;
-    x.zero = (d == 0.0f) || __builtin_isinf(x.r);
+    x.zero = (d == 0.0f) || __builtin_isinf(r);
     return x;
 }
 
@@ -129,6 +133,7 @@ __device__ __forceinline__ bool level_span(const Axis &ax, const Axis &ay, const
 // with the first value past far.
 struct Lattice {
     float tmin, tmax, dt;
+    float inv_dt;       // approximate 1/dt, for index estimates only
     const float *tab;   // growing step only
     int32_t n_tab;
     bool cone;
@@ -149,7 +154,7 @@ struct Lattice {
             }
             return lo;
         }
-        float est = (a - tmin) / dt;
+        float est = (a - tmin) * inv_dt;
         est = fminf(fmaxf(est, 0.0f), 16777216.0f);
         int n = (int)est + 1;
         while (n > 0 && t(n - 1) > a) --n;

@@ -254,6 +254,21 @@ __global__ void vdb_unpack_kernel(GridView g, uint8_t *__restrict__ out) {
     out[i] = v;
 }
 
+// Per-level plane geometry for the samplers, computed once at build time:
+// voxel size h = fl((A-B)/R) (correctly rounded) and an approximate 1/h used
+// only for index estimates.
+__global__ void geom_kernel(const float *__restrict__ boxes, int L, int R, float *__restrict__ geom) {
+    int t = threadIdx.x;
+    if (t >= 3 * L) return;
+    int lev = t / 3, a = t % 3;
+    const float *b = boxes + 6 * lev;
+    float *G = geom + 12 * lev;
+    G[a] = b[a];
+    G[3 + a] = __fdiv_rn(__fsub_rn(b[3 + a], b[a]), (float)R);
+    G[6 + a] = (float)R / (b[3 + a] - b[a]);
+    G[9 + a] = 0.0f;
+}
+
 __global__ void zero_counts_kernel(VdbCounts *c) {
     if (threadIdx.x == 0) *c = VdbCounts{0, 0, 0, 0, 0, 0};
 }
@@ -285,7 +300,7 @@ extern "C" ogv_status ogv_dense_build(int32_t L, int32_t R, const float *boxes, 
     hipStream_t s = (hipStream_t)stream;
     uint64_t n_vox = (uint64_t)L * R * R * R;
     uint64_t n_words = (n_vox + 31) / 32;
-    size_t off_boxes = 0, off_bits = 256;
+    size_t off_boxes = 0, off_geom = 512, off_bits = 1024;
     size_t total = off_bits + n_words * 4;
     ogv_grid *g = new ogv_grid();
     if (hipMalloc(&g->mem, total) != hipSuccess) {
@@ -302,9 +317,11 @@ extern "C" ogv_status ogv_dense_build(int32_t L, int32_t R, const float *boxes, 
     v.L = L;
     v.R = R;
     v.boxes = (const float *)((char *)g->mem + off_boxes);
+    v.geom = (const float *)((char *)g->mem + off_geom);
     v.bits = (const uint32_t *)((char *)g->mem + off_bits);
     hipError_t e = hipMemcpyAsync((void *)v.boxes, g->boxes_host, sizeof(float) * 6 * L, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
+        geom_kernel<<<1, 64, 0, s>>>(v.boxes, L, R, (float *)v.geom);
         dense_pack_kernel<<<(unsigned)((n_words + 255) / 256), 256, 0, s>>>(occ, n_vox, (uint32_t *)v.bits, n_words);
         e = hipGetLastError();
     }
@@ -347,6 +364,7 @@ extern "C" ogv_status ogv_vdb_build(int32_t L, int32_t R, const float *boxes, co
         return at;
     };
     size_t o_boxes = take(sizeof(float) * 6 * L);
+    size_t o_geom = take(sizeof(float) * 12 * L);
     size_t o_counts = take(sizeof(VdbCounts));
     size_t o_root = take(sizeof(int32_t) * b.n_root);
     size_t o_child = take(sizeof(uint64_t) * b.n_root * b.W);
@@ -391,6 +409,7 @@ extern "C" ogv_status ogv_vdb_build(int32_t L, int32_t R, const float *boxes, co
     v.NR = b.NR;
     v.W = b.W;
     v.boxes = (const float *)(m + o_boxes);
+    v.geom = (const float *)(m + o_geom);
     v.root = (const int32_t *)(m + o_root);
     v.child = (const uint64_t *)(m + o_child);
     v.value = (const uint64_t *)(m + o_value);
@@ -407,6 +426,7 @@ extern "C" ogv_status ogv_vdb_build(int32_t L, int32_t R, const float *boxes, co
     hipError_t e = hipMemcpyAsync((void *)v.boxes, g->boxes_host, sizeof(float) * 6 * L, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
         zero_counts_kernel<<<1, 64, 0, s>>>(g->counts_dev);
+        geom_kernel<<<1, 64, 0, s>>>(v.boxes, L, R, (float *)v.geom);
         classify_kernel<<<(unsigned)((b.n_block + 3) / 4), 256, 0, s>>>(b, occ, kind, mixed, masks);
         root_kernel<<<(unsigned)b.n_root, 256, 0, s>>>(b, kind, root_kind, is_node);
         e = hipGetLastError();

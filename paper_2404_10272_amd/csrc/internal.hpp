@@ -48,6 +48,7 @@ struct GridView {
     int32_t L, R;
     int32_t ilog2, S, NR, W;
     const float *boxes;        // [L][6] device copy of the boxes
+    const float *geom;         // [L][12]: B[3], h[3] = fl((A-B)/R), approximate 1/h [3], unused[3]
     const uint32_t *bits;      // dense: bit ((l*R+x)*R+y)*R+z
     const int32_t *root;
     const uint64_t *child;
@@ -83,5 +84,13 @@ namespace ogv {
 bool boxes_valid(int L, int R, const float *boxes, std::string *why);
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Length of the growing-step lattice table for [near, far] (0 for a constant
+// step, -1 if longer than the library handles).
+int32_t cone_table_capacity(float near_t, float far_t, const ogv_step *step);
+
+// Host-side checks of one sampling call's arguments (status + message).
+ogv_status validate_sampling(const ogv_grid *grid, int32_t variant, const float *o, const float *d, int64_t n_rays,
+                             float near_t, float far_t, const ogv_step *step, const char *fn);
 
 }  // namespace ogv

@@ -1,0 +1,689 @@
+// Device-side ray walk shared by the single-scene and batched samplers:
+// dense-grid voxel DDA (the plain method) and VDB + hierarchical DDA
+// (Sec. 2.3, Sec. 3), each in the loop structure of Alg. 1 ("DDA branch")
+// or Alg. 2 ("DDA skip") of the supplementary material.
+//
+// One ray per lane.  A ray is split into segments owned by one cascade level
+// each (finest level wins, Sec. 3); within a segment a cursor walks cells in
+// ray order -- voxels for the dense grid; root tiles, internal-node tiles or
+// leaf voxels for the VDB tree -- and the driver turns maximal runs of
+// occupied cells into parameter intervals (lo, hi].  A visitor converts an
+// interval into its lattice points: the count pass adds their number and
+// keeps the runs, the traversal fill writes the samples.
+#pragma once
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "geometry.hpp"
+#include "internal.hpp"
+
+namespace ogv {
+
+constexpr int kBlock = 256;
+
+// ------------------------------------------------------------------ cursors
+
+// Dense bitfield: every cell is a voxel; one bit lookup per voxel.
+struct DenseCursor {
+    const uint32_t *bits;
+    uint64_t level_base;  // bit index of the level's voxel (0,0,0)
+    int R;
+    Axis A0, A1, A2;
+    int u0, u1, u2;       // ray-order voxel per moving axis
+    int v0, v1, v2;       // voxel index per axis
+    float tn0, tn1, tn2;  // next plane crossing per axis (+inf for zero axes)
+
+    __device__ __forceinline__ bool occupied() const {
+        uint64_t idx = level_base + ((uint64_t)((uint32_t)v0 * (uint32_t)R + (uint32_t)v1) * (uint32_t)R + (uint32_t)v2);
+        return (bits[idx >> 5] >> (idx & 31)) & 1u;
+    }
+    __device__ __forceinline__ float exit(int &axis) const {
+        float hi = tn0;
+        axis = 0;
+        if (tn1 < hi) { hi = tn1; axis = 1; }
+        if (tn2 < hi) { hi = tn2; axis = 2; }
+        return hi;
+    }
+    __device__ __forceinline__ bool step(int axis, float) {
+        if (axis == 0) {
+            if (++u0 >= R) return false;
+            v0 = A0.voxel(u0);
+            tn0 = A0.Tk(u0 + 1);
+        } else if (axis == 1) {
+            if (++u1 >= R) return false;
+            v1 = A1.voxel(u1);
+            tn1 = A1.Tk(u1 + 1);
+        } else {
+            if (++u2 >= R) return false;
+            v2 = A2.voxel(u2);
+            tn2 = A2.Tk(u2 + 1);
+        }
+        return true;
+    }
+};
+
+// The parts of a VDB tree a walk reads; root table and node masks may be
+// staged in LDS (when they fit), leaves are read from global memory.
+struct Tree {
+    const int32_t *root;
+    const uint64_t *child, *value;
+    const uint32_t *rank;
+    const uint64_t *leaves;
+    int ilog2, S, NR, W;
+};
+
+__host__ __device__ inline size_t tree_lds_bytes(int L, int NR, int W) {
+    size_t n_root = (size_t)L * NR * NR * NR;
+    return n_root * (size_t)W * (8 + 8 + 4) + n_root * 4;
+}
+
+// Every thread of the block must call this (it synchronizes).
+template <bool kLds>
+__device__ __forceinline__ Tree load_tree(const GridView &g, uint64_t *smem) {
+    Tree t;
+    t.ilog2 = g.ilog2;
+    t.S = g.S;
+    t.NR = g.NR;
+    t.W = g.W;
+    t.leaves = g.leaves;
+    if (!kLds) {
+        t.root = g.root;
+        t.child = g.child;
+        t.value = g.value;
+        t.rank = g.rank;
+        return t;
+    }
+    // node slots exist for every root cell (the worst case the build sizes for)
+    const int n_root = g.L * g.NR * g.NR * g.NR;
+    const int nw = n_root * g.W;
+    uint64_t *child = smem;
+    uint64_t *value = smem + nw;
+    uint32_t *rank = (uint32_t *)(smem + 2 * nw);
+    int32_t *root = (int32_t *)(rank + nw);
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) {
+        child[i] = g.child[i];
+        value[i] = g.value[i];
+        rank[i] = g.rank[i];
+    }
+    for (int i = threadIdx.x; i < n_root; i += blockDim.x) root[i] = g.root[i];
+    __syncthreads();
+    t.root = root;
+    t.child = child;
+    t.value = value;
+    t.rank = rank;
+    return t;
+}
+
+// VDB tree: the current cell is the largest uniform cell holding the current
+// voxel -- a root tile (D = 8*S voxels per axis), an internal-node tile
+// (D = 8) or a leaf voxel (D = 1).  The cell's exit is the first crossing of
+// its far planes (for D = 1 that is the ordinary voxel step); leaving a tile
+// moves the stepping axis past it and re-locates the other axes exactly at
+// the exit parameter.
+struct VdbCursor {
+    Tree t;
+    int lev, R, sh;
+    Axis A0, A1, A2;
+    int u0, u1, u2;        // ray-order voxel per moving axis
+    int v0, v1, v2;        // voxel index per axis
+    int k0, k1, k2;        // ray-order exit plane of the current cell per axis
+    int D;                 // current cell size in voxels
+    int lblk;              // cached leaf block (packed block coordinates), -1 if none
+    int lbase;             // its first word in the leaf array
+    int wx;                // cached word: voxel x within the leaf
+    uint64_t word;
+
+    __device__ __forceinline__ bool occupied() {
+        // inside the cached leaf: no tree lookup, at most one word load
+        const int blk = ((v0 >> 3) << 20) | ((v1 >> 3) << 10) | (v2 >> 3);
+        if (blk == lblk) {
+            if ((v0 & 7) != wx) {
+                wx = v0 & 7;
+                word = t.leaves[lbase + wx];
+            }
+            D = 1;
+            return (word >> (((v1 & 7) << 3) | (v2 & 7))) & 1ull;
+        }
+        const int NR = t.NR;
+        int ri = ((lev * NR + (v0 >> sh)) * NR + (v1 >> sh)) * NR + (v2 >> sh);
+        int node = t.root[ri];
+        if (node < 0) {
+            D = 8 << t.ilog2;
+            return node == -2;
+        }
+        const int m = t.S - 1;
+        int s = (((v0 >> 3) & m) * t.S + ((v1 >> 3) & m)) * t.S + ((v2 >> 3) & m);
+        int w = node * t.W + (s >> 6);
+        uint64_t cm = t.child[w];
+        uint64_t bit = 1ull << (s & 63);
+        if (!(cm & bit)) {
+            D = 8;
+            return (t.value[w] & bit) != 0;
+        }
+        lblk = blk;
+        lbase = (int)(t.rank[w] + (uint32_t)__popcll(cm & (bit - 1))) * 8;
+        wx = v0 & 7;
+        word = t.leaves[lbase + wx];
+        D = 1;
+        return (word >> (((v1 & 7) << 3) | (v2 & 7))) & 1ull;
+    }
+
+    __device__ __forceinline__ float exit(int &axis) {
+        const float inf = __builtin_huge_valf();
+        const int msk = ~(D - 1);
+        float e0 = inf, e1 = inf, e2 = inf;
+        if (!A0.zero) {
+            int b = v0 & msk;
+            k0 = A0.pos ? b + D : R - b;
+            e0 = A0.Tk(k0);
+        }
+        if (!A1.zero) {
+            int b = v1 & msk;
+            k1 = A1.pos ? b + D : R - b;
+            e1 = A1.Tk(k1);
+        }
+        if (!A2.zero) {
+            int b = v2 & msk;
+            k2 = A2.pos ? b + D : R - b;
+            e2 = A2.Tk(k2);
+        }
+        float hi = e0;
+        axis = 0;
+        if (e1 < hi) { hi = e1; axis = 1; }
+        if (e2 < hi) { hi = e2; axis = 2; }
+        return hi;
+    }
+
+    __device__ __forceinline__ bool step(int axis, float t) {
+        if (axis == 0) {
+            if (k0 >= R) return false;
+            u0 = k0;
+        } else if (D > 1 && !A0.zero) {
+            u0 = A0.advance_to(u0, t, min(k0, R) - 1);
+        }
+        if (axis == 1) {
+            if (k1 >= R) return false;
+            u1 = k1;
+        } else if (D > 1 && !A1.zero) {
+            u1 = A1.advance_to(u1, t, min(k1, R) - 1);
+        }
+        if (axis == 2) {
+            if (k2 >= R) return false;
+            u2 = k2;
+        } else if (D > 1 && !A2.zero) {
+            u2 = A2.advance_to(u2, t, min(k2, R) - 1);
+        }
+        if (!A0.zero) v0 = A0.voxel(u0);
+        if (!A1.zero) v1 = A1.voxel(u1);
+        if (!A2.zero) v2 = A2.voxel(u2);
+        return true;
+    }
+};
+
+// ------------------------------------------------------------------ driver
+
+// Walks cells from the segment start a to its end b (or t_max) and reports
+// maximal occupied runs (lo, hi] to the visitor, from a single call site.
+// kSkip = false is Alg. 1 (every cell visited, branch on occupancy);
+// kSkip = true is Alg. 2 (an inner loop passes all leading empty cells, then
+// the occupied run is marched).
+template <bool kSkip, class Cursor, class Vis>
+__device__ __forceinline__ void drive(Cursor &c, float a, float b, float tmax, Vis &vis) {
+    float lo = a;
+    if (!kSkip) {
+        bool in_run = false;
+        float run_lo = a;
+        while (true) {
+            bool occ = c.occupied();
+            int axis;
+            float hi = c.exit(axis);
+            if (occ && !in_run) {
+                in_run = true;
+                run_lo = lo;
+            }
+            bool end = hi >= b || hi >= tmax;
+            if (!end) end = !c.step(axis, hi);
+            // a run closes at lo on an empty cell, or at this cell's end when the ray ends
+            if (in_run && (!occ || end)) {
+                vis.run(run_lo, occ ? fminf(hi, b) : lo);
+                in_run = false;
+            }
+            if (end) return;
+            lo = hi;
+        }
+    } else {
+        while (true) {
+            bool end = false;
+            while (!c.occupied()) {
+                int axis;
+                float hi = c.exit(axis);
+                if (hi >= b || hi >= tmax || !c.step(axis, hi)) return;
+                lo = hi;
+            }
+            float run_lo = lo, run_hi;
+            while (true) {
+                int axis;
+                float hi = c.exit(axis);
+                end = hi >= b || hi >= tmax;
+                if (!end) end = !c.step(axis, hi);
+                run_hi = fminf(hi, b);
+                lo = hi;
+                if (end || !c.occupied()) break;
+            }
+            vis.run(run_lo, run_hi);
+            if (end) return;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ visitors
+
+// Count pass: number of lattice points in each occupied run, and the runs
+// themselves as lattice-index ranges [n0, n1) (adjacent ranges merged) for
+// the expansion fill.  A ray keeps its first kMaxRuns runs in fixed slots;
+// further runs go to chunks of kMaxRuns slots taken from a shared pool and
+// chained (ray_next -> pool_next -> ...).  If the pool runs dry the ray is
+// marked kRunsLost and the traversal fill writes it instead.
+constexpr int kMaxRuns = 16;
+constexpr int32_t kRunsLost = 0x7fffffff;
+
+struct RunPool {
+    int2 *slots;          // [rays][kMaxRuns]
+    int32_t *ray_next;    // [rays]: first pool chunk of the ray, -1 if none
+    int2 *chunks;         // [cap][kMaxRuns]
+    int32_t *chunk_next;  // [cap]
+    int32_t *head;        // chunks handed out so far
+    int32_t cap;
+};
+
+struct CountVis {
+    const Lattice *lat;
+    int32_t n;            // samples
+    int32_t nr;           // runs stored (kRunsLost: pool exhausted)
+    int64_t ray;
+    RunPool pool;
+    int32_t chunk;        // chunk receiving runs nr.. (when nr >= kMaxRuns)
+    int32_t cur0, cur1;   // run held back for merging (cur1 > cur0 when held)
+
+    __device__ __forceinline__ void begin_level(int, const Axis &, const Axis &, const Axis &) {}
+    __device__ __forceinline__ void store(int32_t a, int32_t b) {
+        if (nr == kRunsLost) return;
+        const int j = nr % kMaxRuns;
+        if (nr < kMaxRuns) {
+            pool.slots[ray * kMaxRuns + nr] = make_int2(a, b);
+        } else {
+            if (j == 0) {
+                int32_t c = atomicAdd(pool.head, 1);
+                if (c >= pool.cap) {
+                    nr = kRunsLost;
+                    return;
+                }
+                pool.chunk_next[c] = -1;
+                if (nr == kMaxRuns) pool.ray_next[ray] = c;
+                else pool.chunk_next[chunk] = c;
+                chunk = c;
+            }
+            pool.chunks[(int64_t)chunk * kMaxRuns + j] = make_int2(a, b);
+        }
+        ++nr;
+    }
+    __device__ __forceinline__ void run(float lo, float hi) {
+        int32_t n0 = lat->first_above(lo);
+        int32_t n1 = lat->first_above(fminf(hi, lat->tmax));
+        if (n1 <= n0) return;
+        n += n1 - n0;
+        if (cur1 > cur0 && cur1 == n0) {
+            cur1 = n1;
+            return;
+        }
+        if (cur1 > cur0) store(cur0, cur1);
+        cur0 = n0;
+        cur1 = n1;
+    }
+    __device__ __forceinline__ void finish() {
+        if (cur1 > cur0) store(cur0, cur1);
+    }
+};
+
+__device__ __forceinline__ CountVis make_count_vis(const Lattice *lat, int64_t ray, const RunPool &pool) {
+    CountVis v;
+    v.lat = lat;
+    v.n = 0;
+    v.nr = 0;
+    v.ray = ray;
+    v.pool = pool;
+    v.chunk = -1;
+    v.cur0 = 0;
+    v.cur1 = 0;
+    pool.ray_next[ray] = -1;
+    return v;
+}
+
+template <bool kVox>
+struct FillVis {
+    const Lattice *lat;
+    int64_t idx, capacity;
+    int32_t ray;
+    int32_t *ray_ids;
+    float *t0, *t1;
+    int32_t *vox;       // written when kVox
+    int lev, R;
+    Axis A0, A1, A2;    // level geometry, for voxel ids only
+
+    __device__ __forceinline__ void begin_level(int l, const Axis &a0, const Axis &a1, const Axis &a2) {
+        lev = l;
+        if (kVox) {
+            A0 = a0;
+            A1 = a1;
+            A2 = a2;
+        }
+    }
+    __device__ __forceinline__ int vcoord(const Axis &A, float t) const {
+        return A.zero ? A.zero_voxel() : A.voxel(A.locate(t, false));
+    }
+    __device__ __forceinline__ void run(float lo, float hi) {
+        int n0 = lat->first_above(lo);
+        int n1 = lat->first_above(fminf(hi, lat->tmax));
+        float tn = lat->t(n0);
+        for (int n = n0; n < n1; ++n) {
+            float tnext = lat->t(n + 1);
+            if (idx < capacity) {
+                ray_ids[idx] = ray;
+                t0[idx] = tn;
+                t1[idx] = tnext;
+                if (kVox) {
+                    int i = vcoord(A0, tn), j = vcoord(A1, tn), k = vcoord(A2, tn);
+                    vox[idx] = ((lev * R + i) * R + j) * R + k;
+                }
+            }
+            ++idx;
+            tn = tnext;
+        }
+    }
+};
+
+// ------------------------------------------------------------------ ray
+
+struct Ray {
+    float o0, o1, o2, d0, d1, d2, r0, r1, r2;
+};
+
+template <bool kVdb, bool kSkip, class Vis>
+__device__ __forceinline__ void march_segment(const GridView &g, const Tree &tree, int lev, const Ray &ray, float a,
+                                              float b, const Lattice &lat, Vis &vis) {
+    const int R = g.R;
+    Axis A0 = load_axis(g.geom, lev, 0, R, ray.o0, ray.d0, ray.r0);
+    Axis A1 = load_axis(g.geom, lev, 1, R, ray.o1, ray.d1, ray.r1);
+    Axis A2 = load_axis(g.geom, lev, 2, R, ray.o2, ray.d2, ray.r2);
+    vis.begin_level(lev, A0, A1, A2);
+    // start at the voxel owning t_min when it lies inside the segment,
+    // else at the voxel owning the parameters just after a
+    const bool after = lat.tmin > a;
+    const float ts = after ? lat.tmin : a;
+    int u0 = A0.zero ? 0 : A0.locate(ts, !after);
+    int u1 = A1.zero ? 0 : A1.locate(ts, !after);
+    int u2 = A2.zero ? 0 : A2.locate(ts, !after);
+    int v0 = A0.zero ? A0.zero_voxel() : A0.voxel(u0);
+    int v1 = A1.zero ? A1.zero_voxel() : A1.voxel(u1);
+    int v2 = A2.zero ? A2.zero_voxel() : A2.voxel(u2);
+    if ((unsigned)v0 >= (unsigned)R || (unsigned)v1 >= (unsigned)R || (unsigned)v2 >= (unsigned)R) return;
+    const float inf = __builtin_huge_valf();
+    if (!kVdb) {
+        DenseCursor c;
+        c.bits = g.bits;
+        c.level_base = (uint64_t)lev * R * R * R;
+        c.R = R;
+        c.A0 = A0; c.A1 = A1; c.A2 = A2;
+        c.u0 = u0; c.u1 = u1; c.u2 = u2;
+        c.v0 = v0; c.v1 = v1; c.v2 = v2;
+        c.tn0 = A0.zero ? inf : A0.Tk(u0 + 1);
+        c.tn1 = A1.zero ? inf : A1.Tk(u1 + 1);
+        c.tn2 = A2.zero ? inf : A2.Tk(u2 + 1);
+        drive<kSkip>(c, a, b, lat.tmax, vis);
+    } else {
+        VdbCursor c;
+        c.t = tree;
+        c.lev = lev;
+        c.R = R;
+        c.sh = 3 + tree.ilog2;
+        c.A0 = A0; c.A1 = A1; c.A2 = A2;
+        c.u0 = u0; c.u1 = u1; c.u2 = u2;
+        c.v0 = v0; c.v1 = v1; c.v2 = v2;
+        c.k0 = c.k1 = c.k2 = 0;
+        c.D = 1;
+        c.lblk = -1;
+        c.lbase = 0;
+        c.wx = 0;
+        c.word = 0;
+        drive<kSkip>(c, a, b, lat.tmax, vis);
+    }
+}
+
+// Level `lev` holds exactly the parameters (E, X]; false if the ray misses it.
+__device__ __forceinline__ bool span_of(const GridView &g, int lev, const Ray &ray, float &E, float &X) {
+    Axis A0 = load_axis(g.geom, lev, 0, g.R, ray.o0, ray.d0, ray.r0);
+    Axis A1 = load_axis(g.geom, lev, 1, g.R, ray.o1, ray.d1, ray.r1);
+    Axis A2 = load_axis(g.geom, lev, 2, g.R, ray.o2, ray.d2, ray.r2);
+    return level_span(A0, A1, A2, E, X);
+}
+
+// All samples of one ray, in increasing t.  The cascade boxes are nested
+// (checked when the grid is built), so level l holds exactly (E_l, X_l] and
+// these intervals nest.  With f the finest level the ray meets and
+// m = L-1-f, segment k = 0..2m runs in t order: for k < m level L-1-k on
+// (E_{L-1-k}, E_{L-2-k}]; for k = m level f on (E_f, X_f]; for k > m level
+// f+(k-m) on (X_{f+k-m-1}, X_{f+k-m}].  Each segment is marched by its level.
+// kL1: the grid has a single level (no cascades), so the level geometry is
+// uniform across the wave.
+template <bool kVdb, bool kSkip, bool kL1 = false, class Vis>
+__device__ __forceinline__ void trace_ray(const GridView &g, const Tree &tree, const float o[3], const float d[3],
+                                          const Lattice &lat, Vis &vis) {
+    if (!(lat.tmin <= lat.tmax)) return;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (!__builtin_isfinite(o[a]) || !__builtin_isfinite(d[a])) return;
+    Ray ray{o[0], o[1], o[2], d[0], d[1], d[2], __fdiv_rn(1.0f, d[0]), __fdiv_rn(1.0f, d[1]), __fdiv_rn(1.0f, d[2])};
+    if (kL1) {
+        float E, X;
+        if (span_of(g, 0, ray, E, X) && E < lat.tmax && X >= lat.tmin)
+            march_segment<kVdb, kSkip>(g, tree, 0, ray, E, X, lat, vis);
+        return;
+    }
+    const int L = g.L;
+    int f = -1;
+    for (int lev = 0; lev < L && f < 0; ++lev) {
+        float E, X;
+        if (span_of(g, lev, ray, E, X)) f = lev;
+    }
+    if (f < 0) return;
+    const int m = L - 1 - f;
+    for (int k = 0; k <= 2 * m; ++k) {
+        // the two levels whose spans bound segment k
+        int lev, inner;
+        if (k < m) {
+            lev = L - 1 - k;
+            inner = lev - 1;
+        } else if (k == m) {
+            lev = f;
+            inner = f;
+        } else {
+            lev = f + (k - m);
+            inner = lev - 1;
+        }
+        float E_l = 0.f, X_l = 0.f, E_i = 0.f, X_i = 0.f;
+        for (int q = 0; q < 2; ++q) {
+            float E, X;
+            span_of(g, q == 0 ? lev : inner, ray, E, X);
+            if (q == 0) {
+                E_l = E;
+                X_l = X;
+            } else {
+                E_i = E;
+                X_i = X;
+            }
+        }
+        float a = k <= m ? E_l : X_i;
+        float b = k < m ? E_i : X_l;
+        if (a >= lat.tmax) break;   // this and every later segment lie past t_max
+        if (a < b && b >= lat.tmin) march_segment<kVdb, kSkip>(g, tree, lev, ray, a, b, lat, vis);
+    }
+}
+
+// ------------------------------------------------------------------ expansion fill
+
+// Expansion fill: a block takes 256 consecutive rays, gathers their kept
+// runs into LDS with each run's first output index, and writes the block's
+// samples with consecutive lanes on consecutive outputs (coalesced): sample
+// j belongs to the last run starting at or before j.  Runs of rays flagged
+// by the count pass are absent; those samples are left to the traversal fill.
+constexpr int kExpandRuns = 1024;
+
+struct OneLattice {       // every ray on one lattice
+    Lattice lat;
+    __device__ __forceinline__ int scene_of(int64_t) const { return 0; }
+    __device__ __forceinline__ float t(int, int n) const { return lat.t(n); }
+};
+
+struct SceneLattices {    // ray r on the lattice of its scene
+    const Lattice *lats;
+    const int64_t *first;  // first global ray of each scene, [n + 1]
+    int n;
+    __device__ __forceinline__ int scene_of(int64_t r) const {
+        int s = 0;
+        while (s + 1 < n && first[s + 1] <= r) ++s;
+        return s;
+    }
+    __device__ __forceinline__ float t(int s, int k) const { return lats[s].t(k); }
+};
+
+__device__ __forceinline__ int64_t block_excl_scan256(int64_t x, int64_t *lds, int64_t &total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int64_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) lds[wid] = x;
+    __syncthreads();
+    int64_t base = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        int64_t v = lds[w];
+        if (w < wid) base += v;
+        total += v;
+    }
+    __syncthreads();
+    return base + x;   // inclusive
+}
+
+// The run of ray r with index k (k < nruns[r]), following the pool chain.
+struct RunReader {
+    const int2 *slots;
+    const int32_t *ray_next;
+    const int2 *chunks;
+    const int32_t *chunk_next;
+};
+
+template <class Lats>
+__device__ __forceinline__ void expand_block(const int64_t *__restrict__ offsets, int64_t n_rays,
+                                             const int32_t *__restrict__ nruns, const RunReader &rd,
+                                             const Lats &lats, int64_t capacity, int32_t *__restrict__ ray_ids,
+                                             float *__restrict__ t0, float *__restrict__ t1, bool vec4) {
+    __shared__ int64_t s_start[kExpandRuns];
+    __shared__ int32_t s_n0[kExpandRuns], s_len[kExpandRuns], s_ray[kExpandRuns];
+    __shared__ int16_t s_scene[kExpandRuns];
+    __shared__ int64_t s_wave[kBlock / 64];
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int nr = 0, scene = 0;
+    int64_t off = 0;
+    if (r < n_rays) {
+        nr = nruns[r];
+        if (nr == kRunsLost) nr = 0;
+        off = offsets[r];
+        scene = lats.scene_of(r);
+    }
+    int64_t total;
+    const int rb = (int)(block_excl_scan256((int64_t)nr, s_wave, total) - nr);
+    for (int c0 = 0; c0 < (int)total; c0 += kExpandRuns) {
+        const int cn = min((int)total - c0, kExpandRuns);
+        int64_t start = off;
+        int32_t chunk = -1;
+        for (int k = 0; k < nr; ++k) {
+            int2 rn;
+            if (k < kMaxRuns) {
+                rn = rd.slots[r * kMaxRuns + k];
+            } else {
+                if (k % kMaxRuns == 0) chunk = k == kMaxRuns ? rd.ray_next[r] : rd.chunk_next[chunk];
+                rn = rd.chunks[(int64_t)chunk * kMaxRuns + k % kMaxRuns];
+            }
+            int idx = rb + k - c0;
+            if (idx >= 0 && idx < cn) {
+                s_start[idx] = start;
+                s_n0[idx] = rn.x;
+                s_len[idx] = rn.y - rn.x;
+                s_ray[idx] = (int32_t)r;
+                s_scene[idx] = (int16_t)scene;
+            }
+            start += rn.y - rn.x;
+        }
+        __syncthreads();
+        const int64_t lo = s_start[0];
+        const int64_t hi = min(s_start[cn - 1] + (int64_t)s_len[cn - 1], capacity);
+        // each lane takes 4 consecutive samples: one search, 16-byte stores
+        for (int64_t j4 = (lo & ~(int64_t)3) + 4 * (int64_t)threadIdx.x; j4 < hi; j4 += 4 * kBlock) {
+            const int64_t jf = j4 < lo ? lo : j4;
+            int a = 0, b = cn - 1;   // last run with start <= jf
+            while (a < b) {
+                int mid = (a + b + 1) >> 1;
+                if (s_start[mid] <= jf) a = mid;
+                else b = mid - 1;
+            }
+            int32_t id[4];
+            float x0[4], x1[4];
+            bool ok[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t j = j4 + q;
+                while (a + 1 < cn && s_start[a + 1] <= j) ++a;
+                const int64_t rel = j - s_start[a];
+                ok[q] = j >= lo && j < hi && rel >= 0 && rel < s_len[a];
+                const int sc = s_scene[a];
+                const int n = s_n0[a] + (int)rel;
+                id[q] = s_ray[a];
+                x0[q] = ok[q] ? lats.t(sc, n) : 0.0f;
+                x1[q] = ok[q] ? lats.t(sc, n + 1) : 0.0f;
+            }
+            if (vec4 && ok[0] && ok[1] && ok[2] && ok[3]) {
+                *reinterpret_cast<int4 *>(ray_ids + j4) = make_int4(id[0], id[1], id[2], id[3]);
+                *reinterpret_cast<float4 *>(t0 + j4) = make_float4(x0[0], x0[1], x0[2], x0[3]);
+                *reinterpret_cast<float4 *>(t1 + j4) = make_float4(x1[0], x1[1], x1[2], x1[3]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (ok[q]) {
+                        ray_ids[j4 + q] = id[q];
+                        t0[j4 + q] = x0[q];
+                        t1[j4 + q] = x1[q];
+                    }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ ray loads
+
+__device__ __forceinline__ void load_ray(const float *origins, const float *dirs, int64_t i, float o[3], float d[3]) {
+    o[0] = origins[3 * i + 0];
+    o[1] = origins[3 * i + 1];
+    o[2] = origins[3 * i + 2];
+    d[0] = dirs[3 * i + 0];
+    d[1] = dirs[3 * i + 1];
+    d[2] = dirs[3 * i + 2];
+}
+
+}  // namespace ogv

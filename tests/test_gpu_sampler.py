@@ -218,6 +218,25 @@ def test_unbounded_cascades(unb, variant):
     assert_same(got, ref, f"unbounded {variant}")
 
 
+@pytest.mark.parametrize("variant", VARIANTS, ids=_VID)
+def test_many_runs_per_ray(variant):
+    """A checkerboard grid gives rays dozens of occupied runs: more than the
+    count pass keeps per ray, so those rays take the traversal fill while the
+    rest are expanded from their runs; the output must not care."""
+    R = 48
+    i, j, k = np.meshgrid(np.arange(R), np.arange(R), np.arange(R), indexing="ij")
+    occ = (((i + j + k) % 2 == 0) | ((i // 8) % 2 == 1)).astype(np.uint8)[None]
+    boxes = np.asarray([[-1, -1, -1, 1, 1, 1]], np.float32)
+    rng = np.random.default_rng(77)
+    o, d = scenes.random_rays(20000, rng, -2.5, 2.5)
+    step = oracle.make_step("const", dt=0.004)
+    ref = oracle.sample_rays(oracle.Scene(occ, boxes), o, d, 0.0, 8.0, step, "dense_branch")
+    g = gpu_grid(variant[0], occ, boxes, 2)
+    for vox in (False, True):
+        got = gpu_sample(g, o, d, 0.0, 8.0, step, variant[1], voxel_ids=vox)
+        assert_same(got, ref, f"checkerboard {variant} vox={vox}")
+
+
 # ------------------------------------------------------------------ structure, edges, errors
 
 @pytest.mark.parametrize("name", ["small", "object", "unbounded"])
