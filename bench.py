@@ -35,6 +35,7 @@ def parse():
                    help="loop structure of the timed VDB sampler (Alg. 1 branch / Alg. 2 skip)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     p.add_argument("--cpu-stride", type=int, default=4, help="oracle baseline uses every k-th ray")
+    p.add_argument("--no-side", action="store_true", help="skip the composite and batched side measurements")
     p.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                    help="only run a plain device copy of MIB MiB (3 times), to calibrate HBM byte counters")
     return p.parse_args()
@@ -57,9 +58,9 @@ class Timed:
     """Count + fill of one grid, with an event before count, between count
     and fill, and after fill, all on the launch stream."""
 
-    def __init__(self, api, torch, grid, w, o, d, variant):
+    def __init__(self, api, torch, grid, w, o, d, variant, image_width=0):
         self.torch = torch
-        self.sp = api.Sampler(grid, w.n_rays, w.near, w.far, w.step, variant)
+        self.sp = api.Sampler(grid, w.n_rays, w.near, w.far, w.step, variant, image_width=image_width)
         self.o, self.d = o, d
         self.sp.count(o, d)
         torch.cuda.synchronize()
@@ -95,6 +96,79 @@ class Timed:
         count_ms = [e[0].elapsed_time(e[1]) for e in evs]
         fill_ms = [e[1].elapsed_time(e[2]) for e in evs]
         return total_ms / steps, sum(count_ms) / steps, sum(fill_ms) / steps
+
+
+def time_events(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def composite_side(api, torch, scenes, hdda, N, steps):
+    """Fused composite forward and backward over the step's packed samples
+    (sigma ~ exp(N(0,1)), rgb ~ U[0,1]^3 per sample)."""
+    S = hdda.S
+    sigma, rgb, _ = scenes.composite_inputs(S, N)
+    sig = torch.from_numpy(sigma).cuda()
+    col = torch.from_numpy(rgb).cuda()
+    off = hdda.sp.offsets
+    g_rgb = torch.ones((N, 3), device="cuda")
+    g_a = torch.ones(N, device="cuda")
+    fwd = time_events(torch, lambda: api.composite_forward(off, hdda.t0, hdda.t1, sig, col), steps, 2)
+    bwd = time_events(torch, lambda: api.composite_backward(off, hdda.t0, hdda.t1, sig, col, g_rgb, g_a), steps, 2)
+    fb = 20 * S + 8 * N + 16 * N            # samples read, offsets read, pixels written
+    bb = 2 * 20 * S + 8 * N + 16 * N + 16 * S
+    return {"forward_ms": fwd, "backward_ms": bwd, "forward_GBps": fb / (fwd * 1e-3) / 1e9,
+            "backward_GBps": bb / (bwd * 1e-3) / 1e9, "samples": S}
+
+
+def batched_side(api, torch, scenes, steps):
+    """16 scenes (grids 64^3..256^3, 2-20 % occupied, 64^2..1024^2 rays):
+    one graph-captured batched pass vs 16 sequential single-scene calls."""
+    ws = scenes.batched()
+    gs = []
+    for w in ws:
+        occ = torch.from_numpy(w.occ).cuda()
+        gs.append((api.build_vdb(occ, w.boxes, w.ilog2), torch.from_numpy(w.origins).cuda(),
+                   torch.from_numpy(w.dirs).cuda(), w.near, w.far, w.step, w.image[0]))
+    batch = api.Batch(gs, "branch")
+    info = batch.info()
+    z = torch.zeros(1, dtype=torch.int32, device="cuda")
+    zf = torch.zeros(1, device="cuda")
+    batch.launch(z[:0], zf[:0], zf[:0], graph=False)
+    torch.cuda.synchronize()
+    S = int(batch.offsets[-1].item())
+    ids = torch.empty(S, dtype=torch.int32, device="cuda")
+    t0 = torch.empty(S, device="cuda")
+    t1 = torch.empty(S, device="cuda")
+    graph_ms = time_events(torch, lambda: batch.launch(ids, t0, t1, graph=True), steps, 2)
+    eager_ms = time_events(torch, lambda: batch.launch(ids, t0, t1, graph=False), steps, 2)
+    seq = []
+    for g, o, d, near, far, step, width in gs:
+        sp = api.Sampler(g, o.shape[0], near, far, step, "branch", image_width=width)
+        sp.count(o, d)
+        torch.cuda.synchronize()
+        n = int(sp.offsets[-1].item())
+        seq.append((sp, o, d, torch.empty(n, dtype=torch.int32, device="cuda"), torch.empty(n, device="cuda"),
+                    torch.empty(n, device="cuda")))
+
+    def sequential():
+        for sp, o, d, i_, a_, b_ in seq:
+            sp.rays(o, d, i_, a_, b_)
+
+    seq_ms = time_events(torch, sequential, steps, 2)
+    N = info["n_rays"]
+    return {"scenes": len(ws), "rays": N, "samples": S, "graph_ms": graph_ms, "eager_ms": eager_ms,
+            "sequential_ms": seq_ms, "rays_per_s": N / (graph_ms * 1e-3),
+            "sequential_rays_per_s": N / (seq_ms * 1e-3), "speedup_vs_sequential": seq_ms / graph_ms,
+            "tune": {"chunk": info["chunk"], "blocks_per_cu": info["blocks_per_cu"], "tuned": info["tuned"]}}
 
 
 def cpu_baseline(w, stride):
@@ -149,28 +223,43 @@ def main():
     vinfo, dinfo = vdb.info(), dense.info()
 
     other = "skip" if args.variant == "branch" else "branch"
-    hdda = Timed(api, torch, vdb, w, o, d, args.variant)
-    hdda_other = Timed(api, torch, vdb, w, o, d, other)
-    plain = Timed(api, torch, dense, w, o, d, "branch")
-    plain_skip = Timed(api, torch, dense, w, o, d, "skip")
+    W = w.image[0]
+    hdda = Timed(api, torch, vdb, w, o, d, args.variant, W)
+    hdda_other = Timed(api, torch, vdb, w, o, d, other, W)
+    hdda_rows = Timed(api, torch, vdb, w, o, d, args.variant, 0)
+    plain = Timed(api, torch, dense, w, o, d, "branch", W)
+    plain_skip = Timed(api, torch, dense, w, o, d, "skip", W)
+    plain_rows = Timed(api, torch, dense, w, o, d, "branch", 0)
     assert hdda.S == plain.S == hdda_other.S == plain_skip.S, "samplers disagree on the sample count"
     ms, count_ms, fill_ms = hdda.run(args.steps, args.warmup)
     oms, ocount_ms, ofill_ms = hdda_other.run(args.steps, args.warmup)
+    rms, _, _ = hdda_rows.run(args.steps, args.warmup)
     dms, dcount_ms, dfill_ms = plain.run(args.steps, args.warmup)
     dsms, dscount_ms, dsfill_ms = plain_skip.run(args.steps, args.warmup)
+    drms, _, _ = plain_rows.run(args.steps, args.warmup)
     N, S = w.n_rays, hdda.S
     G = vinfo["bytes"]
-    fill_bytes = 24 * N + 8 * N + 12 * S + G          # rays + offsets read, samples written, tree read
-    step_bytes = 24 * N + 8 * (N + 1) + 12 * S + G    # whole-step algorithmic bytes
-    achieved = fill_bytes / (fill_ms * 1e-3) / 1e9
+    # maximal lattice-contiguous runs (what the count kernel stores), from the
+    # packed output, outside the timed region
+    ids, t0, t1 = hdda.ids, hdda.t0, hdda.t1
+    runs = int(1 + ((ids[1:] != ids[:-1]) | (t0[1:] != t1[:-1])).sum().item()) if S > 0 else 0
+    # algorithmic bytes per launch
+    count_bytes = 24 * N + 12 * N + 8 * runs + G          # rays read; counts, run counts, chain heads, runs written
+    fill_bytes = 8 * N + 4 * N + 8 * runs + 12 * S        # offsets, run counts, runs read; samples written
+    step_bytes = 24 * N + 8 * (N + 1) + 12 * S + G        # the call's inputs and outputs
+    if count_ms >= fill_ms:
+        dom = {"kernel": "count_kernel<vdb> + scan", "bytes": count_bytes, "ms": count_ms}
+    else:
+        dom = {"kernel": "expand_kernel (+ fallback fill)", "bytes": fill_bytes, "ms": fill_ms}
+    achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
 
     traffic = None
-    tpath = os.path.join(ROOT, "profiles", "traffic_fill_vdb_object800.json")
+    tpath = os.path.join(ROOT, "profiles", "traffic_object800.json")
     if os.path.exists(tpath):
         try:
             rec = json.load(open(tpath))
             if rec.get("kernel_source_sha") == _kernel_sha():
-                traffic = rec.get("bytes_per_launch")
+                traffic = rec.get("bytes_per_launch", {}).get(dom["kernel"])
         except Exception:
             traffic = None
 
@@ -190,12 +279,14 @@ def main():
         "config": {"workload": "object-scene: 128^3 occupancy grid over [-1.5,1.5]^3 (6.0% occupied, "
                                "noise on 12 ellipsoid shells), 800x800 rays from radius 4, 40 deg FOV, "
                                "near 2, far 6, step 5e-3; VDB internal nodes 16^3 over 8^3 leaves",
-                   "rays": N, "samples": S, "variant": args.variant},
+                   "rays": N, "samples": S, "variant": args.variant, "lanes": "8x8 pixel tiles"},
         "samples_per_s": S / (ms * 1e-3),
         "vdb": {"ms_per_step": ms, "count_scan_ms": count_ms, "fill_ms": fill_ms, "rays_per_s": N / (ms * 1e-3),
                 "bytes": G, "leaves": vinfo["n_leaves"], "build_ms": build_ms},
         "vdb_" + other: {"ms_per_step": oms, "count_scan_ms": ocount_ms, "fill_ms": ofill_ms,
                          "rays_per_s": N / (oms * 1e-3)},
+        "vdb_row_major_lanes": {"ms_per_step": rms, "rays_per_s": N / (rms * 1e-3)},
+        "dense_row_major_lanes": {"ms_per_step": drms, "rays_per_s": N / (drms * 1e-3)},
         "dense": {"ms_per_step": dms, "count_scan_ms": dcount_ms, "fill_ms": dfill_ms,
                   "rays_per_s": N / (dms * 1e-3), "samples_per_s": S / (dms * 1e-3), "bytes": dinfo["bytes"],
                   "variant": "branch"},
@@ -203,10 +294,19 @@ def main():
                        "rays_per_s": N / (dsms * 1e-3)},
         "speedup_vs_dense": dms / ms,
         "step_bytes": step_bytes,
-        "roofline": {"bound": "hbm", "kernel": "fill_kernel<vdb>", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "runs": runs,
+        "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes": fill_bytes, "avg_ms": fill_ms},
+                     "algorithmic_bytes": dom["bytes"], "avg_ms": dom["ms"],
+                     "other_stage": {"kernel": "expand_kernel (+ fallback fill)" if dom["ms"] == count_ms
+                                     else "count_kernel<vdb> + scan",
+                                     "algorithmic_bytes": fill_bytes if dom["ms"] == count_ms else count_bytes,
+                                     "avg_ms": fill_ms if dom["ms"] == count_ms else count_ms}},
     }
+    if not args.no_side:
+        line["composite"] = composite_side(api, torch, scenes, hdda, N, min(args.steps, 20))
+        line["batched"] = batched_side(api, torch, scenes, min(args.steps, 10))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_stride)
     print(json.dumps(line), flush=True)
@@ -215,7 +315,7 @@ def main():
 def _kernel_sha():
     import hashlib
     h = hashlib.sha256()
-    for f in ["sample.hip", "geometry.hpp", "scan.hpp", "internal.hpp"]:
+    for f in ["sample.hip", "trace.hpp", "geometry.hpp", "scan.hpp", "internal.hpp"]:
         with open(os.path.join(ROOT, "paper_2404_10272_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -66,6 +66,15 @@ typedef int32_t ogv_status;
 #define OGV_BRANCH 0
 #define OGV_SKIP 1
 
+/* Options of a sampling call (NULL means {OGV_BRANCH, 0}).  image_width > 0
+ * says the rays are the row-major pixels of an image that wide; lanes then
+ * take 8x8 pixel tiles so neighbouring rays walk together.  It changes only
+ * speed, never the samples or their order. */
+typedef struct {
+    int32_t variant;      /* OGV_BRANCH or OGV_SKIP */
+    int32_t image_width;  /* >= 0 */
+} ogv_sample_opts;
+
 #define OGV_STEP_CONST 0 /* t_n = near + n*dt            (NeRF-Synthetic, Sec. 3) */
 #define OGV_STEP_CONE 1  /* dt_n = max(t_n*cone, dt_min) (Mip-NeRF 360, Sec. 3) */
 
@@ -132,7 +141,7 @@ ogv_status ogv_sample_workspace_size(int64_t n_rays, float near_t, float far_t, 
  *                          sample of ray i, offsets[n_rays] = total.
  *   ws_dev, ws_bytes       workspace of ogv_sample_workspace_size bytes.
  * Dense grids march voxels; VDB grids use the hierarchical DDA. */
-ogv_status ogv_sample_count(const ogv_grid *grid, int32_t variant, const float *origins_dev, const float *dirs_dev,
+ogv_status ogv_sample_count(const ogv_grid *grid, const ogv_sample_opts *opts, const float *origins_dev, const float *dirs_dev,
                             int64_t n_rays, float near_t, float far_t, const ogv_step *step_host,
                             int64_t *offsets_dev, void *ws_dev, size_t ws_bytes, void *stream);
 
@@ -146,7 +155,7 @@ ogv_status ogv_sample_count(const ogv_grid *grid, int32_t variant, const float *
  *   ray_ids_dev int32 [capacity], t0_dev/t1_dev float32 [capacity].
  *   voxel_ids_dev     nullable int32 [capacity]: ((l*R+i)*R+j)*R+k of the
  *                     voxel owning t0 (debug/parity output, slower). */
-ogv_status ogv_sample_fill(const ogv_grid *grid, int32_t variant, const float *origins_dev, const float *dirs_dev,
+ogv_status ogv_sample_fill(const ogv_grid *grid, const ogv_sample_opts *opts, const float *origins_dev, const float *dirs_dev,
                            int64_t n_rays, float near_t, float far_t, const ogv_step *step_host,
                            const int64_t *offsets_dev, int64_t capacity, int32_t *ray_ids_dev, float *t0_dev,
                            float *t1_dev, int32_t *voxel_ids_dev, void *ws_dev, size_t ws_bytes, void *stream);
@@ -155,7 +164,7 @@ ogv_status ogv_sample_fill(const ogv_grid *grid, int32_t variant, const float *o
  * (capacity mode): offsets_dev as in ogv_sample_count; samples beyond
  * `capacity` are dropped and *overflow_dev (int32) is set to 1, else 0.
  * The caller reads offsets[n_rays] to learn the total. */
-ogv_status ogv_sample_rays(const ogv_grid *grid, int32_t variant, const float *origins_dev, const float *dirs_dev,
+ogv_status ogv_sample_rays(const ogv_grid *grid, const ogv_sample_opts *opts, const float *origins_dev, const float *dirs_dev,
                            int64_t n_rays, float near_t, float far_t, const ogv_step *step_host,
                            int64_t *offsets_dev, int64_t capacity, int32_t *ray_ids_dev, float *t0_dev,
                            float *t1_dev, int32_t *voxel_ids_dev, int32_t *overflow_dev, void *ws_dev,
@@ -191,6 +200,7 @@ typedef struct {
     int64_t n_rays;
     float near_t, far_t;
     ogv_step step;
+    int32_t image_width;                 /* as in ogv_sample_opts */
 } ogv_scene;
 
 typedef struct {

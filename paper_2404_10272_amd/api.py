@@ -33,9 +33,14 @@ class _Info(ctypes.Structure):
                 ("n_root_tiles_full", ctypes.c_int64), ("n_root_tiles_empty", ctypes.c_int64)]
 
 
+class _Opts(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("image_width", ctypes.c_int32)]
+
+
 class _Scene(ctypes.Structure):
     _fields_ = [("grid", ctypes.c_void_p), ("origins", ctypes.c_void_p), ("dirs", ctypes.c_void_p),
-                ("n_rays", ctypes.c_int64), ("near_t", ctypes.c_float), ("far_t", ctypes.c_float), ("step", _Step)]
+                ("n_rays", ctypes.c_int64), ("near_t", ctypes.c_float), ("far_t", ctypes.c_float), ("step", _Step),
+                ("image_width", ctypes.c_int32)]
 
 
 class _Tune(ctypes.Structure):
@@ -58,11 +63,12 @@ SIGNATURES = {
     "ogv_grid_to_dense": (I32, [VP, VP, VP]),
     "ogv_grid_destroy": (None, [VP]),
     "ogv_sample_workspace_size": (I32, [I64, F32, F32, ctypes.POINTER(_Step), ctypes.POINTER(SZ)]),
-    "ogv_sample_count": (I32, [VP, I32, VP, VP, I64, F32, F32, ctypes.POINTER(_Step), VP, VP, SZ, VP]),
-    "ogv_sample_fill": (I32, [VP, I32, VP, VP, I64, F32, F32, ctypes.POINTER(_Step), VP, I64, VP, VP, VP, VP, VP,
-                              SZ, VP]),
-    "ogv_sample_rays": (I32, [VP, I32, VP, VP, I64, F32, F32, ctypes.POINTER(_Step), VP, I64, VP, VP, VP, VP, VP,
-                              VP, SZ, VP]),
+    "ogv_sample_count": (I32, [VP, ctypes.POINTER(_Opts), VP, VP, I64, F32, F32, ctypes.POINTER(_Step), VP, VP, SZ,
+                               VP]),
+    "ogv_sample_fill": (I32, [VP, ctypes.POINTER(_Opts), VP, VP, I64, F32, F32, ctypes.POINTER(_Step), VP, I64, VP, VP,
+                              VP, VP, VP, SZ, VP]),
+    "ogv_sample_rays": (I32, [VP, ctypes.POINTER(_Opts), VP, VP, I64, F32, F32, ctypes.POINTER(_Step), VP, I64, VP, VP,
+                              VP, VP, VP, VP, SZ, VP]),
     "ogv_composite_fwd": (I32, [VP, I64, VP, VP, VP, VP, VP, VP, VP]),
     "ogv_composite_bwd": (I32, [VP, I64, VP, VP, VP, VP, VP, VP, VP, VP, VP]),
     "ogv_batch_create": (I32, [ctypes.POINTER(_Scene), I32, I32, ctypes.POINTER(_Tune), ctypes.POINTER(VP), VP]),
@@ -199,46 +205,47 @@ class Sampler:
     """Reusable sampling call on one grid with fixed ray count and lattice;
     holds the workspace so repeated calls allocate nothing but outputs."""
 
-    def __init__(self, grid, n_rays, near, far, step, variant="skip", device="cuda"):
+    def __init__(self, grid, n_rays, near, far, step, variant="branch", device="cuda", image_width=0):
         self.grid = grid
         self.n = int(n_rays)
         self.near, self.far = float(near), float(far)
         self.step = step if isinstance(step, _Step) else make_step(step)
         self.variant = _variant(variant)
+        self.opts = _Opts(self.variant, int(image_width))
         self.ws_bytes = workspace_bytes(self.n, self.near, self.far, self.step)
         self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
         self.offsets = torch.empty(self.n + 1, dtype=torch.int64, device=device)
         self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
 
     def count(self, o, d, stream=None):
-        _check(lib().ogv_sample_count(self.grid.handle, self.variant, _ptr(o), _ptr(d), self.n, self.near, self.far,
+        _check(lib().ogv_sample_count(self.grid.handle, ctypes.byref(self.opts), _ptr(o), _ptr(d), self.n, self.near, self.far,
                                       ctypes.byref(self.step), _ptr(self.offsets), _ptr(self.ws), self.ws_bytes,
                                       _stream(stream)))
         return self.offsets
 
     def fill(self, o, d, ray_ids, t0, t1, voxel_ids=None, stream=None):
-        _check(lib().ogv_sample_fill(self.grid.handle, self.variant, _ptr(o), _ptr(d), self.n, self.near, self.far,
+        _check(lib().ogv_sample_fill(self.grid.handle, ctypes.byref(self.opts), _ptr(o), _ptr(d), self.n, self.near, self.far,
                                      ctypes.byref(self.step), _ptr(self.offsets), int(t0.numel()), _ptr(ray_ids),
                                      _ptr(t0), _ptr(t1), _ptr(voxel_ids), _ptr(self.ws), self.ws_bytes,
                                      _stream(stream)))
 
     def rays(self, o, d, ray_ids, t0, t1, voxel_ids=None, stream=None):
         """Count + scan + fill with no host round trip (capacity = len(t0))."""
-        _check(lib().ogv_sample_rays(self.grid.handle, self.variant, _ptr(o), _ptr(d), self.n, self.near, self.far,
+        _check(lib().ogv_sample_rays(self.grid.handle, ctypes.byref(self.opts), _ptr(o), _ptr(d), self.n, self.near, self.far,
                                      ctypes.byref(self.step), _ptr(self.offsets), int(t0.numel()), _ptr(ray_ids),
                                      _ptr(t0), _ptr(t1), _ptr(voxel_ids), _ptr(self.overflow), _ptr(self.ws),
                                      self.ws_bytes, _stream(stream)))
         return self.offsets, self.overflow
 
 
-def sample_rays(grid, origins, dirs, near, far, step, variant="skip", voxel_ids=False):
+def sample_rays(grid, origins, dirs, near, far, step, variant="branch", voxel_ids=False, image_width=0):
     """Packed samples of every ray: dict(offsets[N+1], ray_ids[S], t0[S], t1[S], voxel_ids[S]?).
 
     Counts first, reads the total (one device->host sync), allocates the
     exact outputs, then fills.
     """
     o, d, n = _rays(origins, dirs)
-    sp = Sampler(grid, n, near, far, step, variant, device=o.device)
+    sp = Sampler(grid, n, near, far, step, variant, device=o.device, image_width=image_width)
     offsets = sp.count(o, d)
     total = int(offsets[n].item())
     dev = o.device
@@ -258,19 +265,21 @@ def sample_rays(grid, origins, dirs, near, far, step, variant="skip", voxel_ids=
 class Batch:
     """Many scenes sampled in one graph-captured pass (see ogv_batch_create).
 
-    scenes: list of (grid, origins, dirs, near, far, step).  tune: None to
-    autotune, or (chunk, blocks_per_cu).  The grids and ray tensors are kept
-    alive by this object.
+    scenes: list of (grid, origins, dirs, near, far, step[, image_width]).
+    tune: None to autotune, or (chunk, blocks_per_cu).  The grids and ray
+    tensors are kept alive by this object.
     """
 
-    def __init__(self, scenes, variant="skip", tune=None, stream=None):
+    def __init__(self, scenes, variant="branch", tune=None, stream=None):
         self._keep = []
         arr = (_Scene * len(scenes))()
-        for i, (grid, o, d, near, far, step) in enumerate(scenes):
+        for i, sc in enumerate(scenes):
+            grid, o, d, near, far, step = sc[:6]
+            width = int(sc[6]) if len(sc) > 6 else 0
             o, d, n = _rays(o, d)
             self._keep += [grid, o, d]
             st = step if isinstance(step, _Step) else make_step(step)
-            arr[i] = _Scene(grid.handle, o.data_ptr(), d.data_ptr(), n, float(near), float(far), st)
+            arr[i] = _Scene(grid.handle, o.data_ptr(), d.data_ptr(), n, float(near), float(far), st, width)
         t = None if tune is None else ctypes.byref(_Tune(int(tune[0]), int(tune[1])))
         h = ctypes.c_void_p()
         _check(lib().ogv_batch_create(arr, len(scenes), _variant(variant), t, ctypes.byref(h), _stream(stream)))

@@ -33,9 +33,11 @@ struct SceneDesc {
     GridView g;
     const float *o, *d;
     int64_t n;       // rays of the scene
+    int64_t nt;      // threads walking them (more than n when image-tiled)
     int64_t first;   // its first global ray
     int64_t item0;   // its first queue item
     Lattice lat;
+    int32_t width;   // image width for 8x8 tiling, 0 for none
 };
 
 // zeroes the queue head and the run-pool head (queue[0], queue[1])
@@ -74,19 +76,21 @@ __global__ void __launch_bounds__(kBlock) batch_count_kernel(const SceneDesc *__
         if (item >= n_items) return;
         const SceneDesc *sc = scenes + scene_of_item(scenes, n_scenes, item);
         const int64_t r0 = (item - sc->item0) * (int64_t)chunk;
-        const int64_t r1 = min(r0 + (int64_t)chunk, sc->n);
-        Lattice lat = sc->lat;
-        lat.inv_dt = lat.cone ? 0.0f : __builtin_amdgcn_rcpf(lat.dt);
+        const int64_t r1 = min(r0 + (int64_t)chunk, sc->nt);
+        const Lattice lat = sc->lat;
         const GridView g = sc->g;
         const Tree tree = load_tree<false>(g, nullptr);
-        for (int64_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
+        const CountCtx ctx{lat, pool};
+        for (int64_t tr = r0 + threadIdx.x; tr < r1; tr += kBlock) {
+            const int64_t r = ray_of_thread(tr, sc->n, sc->width);
+            if (r < 0) continue;
             float o[3], d[3];
             load_ray(sc->o, sc->d, r, o, d);
             const int64_t gr = sc->first + r;
-            CountVis vis = make_count_vis(&lat, gr, pool);
-            if (g.kind == 1) trace_ray<true, kSkip>(g, tree, o, d, lat, vis);
-            else trace_ray<false, kSkip>(g, tree, o, d, lat, vis);
-            vis.finish();
+            CountVis vis = make_count_vis(gr, pool);
+            if (g.kind == 1) trace_ray<true, kSkip>(g, tree, o, d, lat, vis, ctx);
+            else trace_ray<false, kSkip>(g, tree, o, d, lat, vis, ctx);
+            vis.finish(ctx);
             counts[gr] = vis.n;
             nruns[gr] = vis.nr;
         }
@@ -115,25 +119,18 @@ __global__ void __launch_bounds__(kBlock) batch_overflow_fill_kernel(
     const int64_t first_out = offsets[gr];
     if (first_out >= capacity) return;
     const SceneDesc *sc = scenes + scene_of_ray(scenes, n_scenes, gr);
-    Lattice lat = sc->lat;
-    lat.inv_dt = lat.cone ? 0.0f : __builtin_amdgcn_rcpf(lat.dt);
+    const Lattice lat = sc->lat;
     const GridView g = sc->g;
     const Tree tree = load_tree<false>(g, nullptr);
     float o[3], d[3];
     load_ray(sc->o, sc->d, gr - sc->first, o, d);
+    const FillCtx ctx{lat, capacity, ray_ids, t0, t1, nullptr, g.R};
     FillVis<false> vis;
-    vis.lat = &lat;
     vis.idx = first_out;
-    vis.capacity = capacity;
     vis.ray = (int32_t)gr;
-    vis.ray_ids = ray_ids;
-    vis.t0 = t0;
-    vis.t1 = t1;
-    vis.vox = nullptr;
     vis.lev = 0;
-    vis.R = g.R;
-    if (g.kind == 1) trace_ray<true, kSkip>(g, tree, o, d, lat, vis);
-    else trace_ray<false, kSkip>(g, tree, o, d, lat, vis);
+    if (g.kind == 1) trace_ray<true, kSkip>(g, tree, o, d, lat, vis, ctx);
+    else trace_ray<false, kSkip>(g, tree, o, d, lat, vis, ctx);
 }
 
 // growing-step lattice of one scene (one thread), padded past its length
@@ -188,7 +185,7 @@ hipError_t upload_desc(ogv_batch *b, int chunk, hipStream_t s) {
     int64_t item = 0;
     for (SceneDesc &d : b->desc) {
         d.item0 = item;
-        item += (d.n + chunk - 1) / chunk;
+        item += (d.nt + chunk - 1) / chunk;
     }
     b->n_items = item;
     hipError_t e = hipMemcpyAsync(b->desc_dev, b->desc.data(), sizeof(SceneDesc) * b->n_scenes,
@@ -298,6 +295,10 @@ extern "C" ogv_status ogv_batch_create(const ogv_scene *scenes, int32_t n, int32
             release(b);
             return st;
         }
+        if (sc.image_width < 0) {
+            release(b);
+            OGV_FAIL(OGV_ERR_INVALID, pre + "image_width < 0");
+        }
         tab_cap[i] = cone_table_capacity(sc.near_t, sc.far_t, &sc.step);
         tab_words += (size_t)std::max(tab_cap[i], 0);
         b->ray_base.push_back(total);
@@ -359,12 +360,13 @@ extern "C" ogv_status ogv_batch_create(const ogv_scene *scenes, int32_t n, int32
         d.o = sc.origins_dev;
         d.d = sc.dirs_dev;
         d.n = sc.n_rays;
+        d.width = sc.image_width;
+        d.nt = tiled_threads(sc.n_rays, sc.image_width);
         d.first = b->ray_base[i];
         Lattice &L = d.lat;
         L.tmin = sc.near_t;
         L.tmax = sc.far_t;
         L.dt = sc.step.dt;
-        L.inv_dt = 0.0f;
         L.cone = sc.step.kind == OGV_STEP_CONE;
         L.tab = nullptr;
         L.n_tab = 0;

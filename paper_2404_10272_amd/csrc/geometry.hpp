@@ -133,7 +133,6 @@ __device__ __forceinline__ bool level_span(const Axis &ax, const Axis &ay, const
 // with the first value past far.
 struct Lattice {
     float tmin, tmax, dt;
-    float inv_dt;       // approximate 1/dt, for index estimates only
     const float *tab;   // growing step only
     int32_t n_tab;
     bool cone;
@@ -154,7 +153,7 @@ struct Lattice {
             }
             return lo;
         }
-        float est = (a - tmin) * inv_dt;
+        float est = (a - tmin) * __builtin_amdgcn_rcpf(dt);   // estimate only
         est = fminf(fmaxf(est, 0.0f), 16777216.0f);
         int n = (int)est + 1;
         while (n > 0 && t(n - 1) > a) --n;

@@ -12,6 +12,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <string>
 
 #include "geometry.hpp"
@@ -31,19 +32,73 @@ template <bool kVdb, bool kSkip, bool kLds, bool kL1>
 __global__ void __launch_bounds__(kBlock) count_kernel(GridView g, const float *__restrict__ origins,
                                                        const float *__restrict__ dirs, int64_t n_rays, Lattice lat,
                                                        int32_t *__restrict__ counts, int32_t *__restrict__ nruns,
-                                                       RunPool pool) {
+                                                       RunPool pool, int image_width) {
     extern __shared__ uint64_t smem[];
     Tree tree = kVdb ? load_tree<kLds>(g, smem) : Tree{};
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n_rays) return;
+    const int64_t i = ray_of_thread((int64_t)blockIdx.x * kBlock + threadIdx.x, n_rays, image_width);
+    if (i < 0) return;
     float o[3], d[3];
     load_ray(origins, dirs, i, o, d);
-    lat.inv_dt = lat.cone ? 0.0f : __builtin_amdgcn_rcpf(lat.dt);
-    CountVis vis = make_count_vis(&lat, i, pool);
-    trace_ray<kVdb, kSkip, kL1>(g, tree, o, d, lat, vis);
-    vis.finish();
+    const CountCtx ctx{lat, pool};
+    CountVis vis = make_count_vis(i, pool);
+    trace_ray<kVdb, kSkip, kL1>(g, tree, o, d, lat, vis, ctx);
+    vis.finish(ctx);
     counts[i] = vis.n;
     nruns[i] = vis.nr;
+}
+
+// Counting with lane refill (single-level grids, Alg. 1 loop): wave w owns
+// ray slots [w*per_wave, (w+1)*per_wave) in tile order; whenever lanes are
+// idle they take the next slots, ranked by a ballot, so the wave keeps
+// stepping full until its slots run out.
+template <bool kVdb, bool kLds>
+__global__ void __launch_bounds__(kBlock) count_refill_kernel(GridView g, const float *__restrict__ origins,
+                                                              const float *__restrict__ dirs, int64_t n_rays,
+                                                              Lattice lat, int32_t *__restrict__ counts,
+                                                              int32_t *__restrict__ nruns, RunPool pool,
+                                                              int image_width, int64_t n_slots, int per_wave) {
+    extern __shared__ uint64_t smem[];
+    Tree tree = kVdb ? load_tree<kLds>(g, smem) : Tree{};
+    const CountCtx ctx{lat, pool};
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int64_t last = min((wave + 1) * (int64_t)per_wave, n_slots);
+    int64_t next = wave * (int64_t)per_wave;
+    Walk<kVdb> w;
+    CountVis vis;
+    int64_t ray = -1;
+    bool active = false;
+    while (true) {
+        const uint64_t idle = __ballot(!active);
+        if (idle != 0 && next < last) {
+            if (!active) {
+                const int64_t slot = next + __popcll(idle & below);
+                ray = slot < last ? ray_of_thread(slot, n_rays, image_width) : -1;
+                if (ray >= 0) {
+                    float o[3], d[3];
+                    load_ray(origins, dirs, ray, o, d);
+                    vis = make_count_vis(ray, pool);
+                    active = walk_begin(w, g, tree, o, d, lat, vis);
+                    if (!active) {
+                        counts[ray] = 0;
+                        nruns[ray] = 0;
+                    }
+                }
+            }
+            next += __popcll(idle);
+        }
+        if (__ballot(active) == 0) {
+            if (next >= last) break;
+            continue;
+        }
+        if (active && walk_step(w, lat.tmax, vis, ctx)) {
+            vis.finish(ctx);
+            counts[ray] = vis.n;
+            nruns[ray] = vis.nr;
+            active = false;
+        }
+    }
 }
 
 // Traversal fill: re-walks ray i and writes its samples from offsets[i].
@@ -66,19 +121,12 @@ __global__ void __launch_bounds__(kBlock) fill_kernel(GridView g, const float *_
     if (first >= capacity) return;
     float o[3], d[3];
     load_ray(origins, dirs, i, o, d);
-    lat.inv_dt = lat.cone ? 0.0f : __builtin_amdgcn_rcpf(lat.dt);
+    const FillCtx ctx{lat, capacity, ray_ids, t0, t1, vox, g.R};
     FillVis<kVox> vis;
-    vis.lat = &lat;
     vis.idx = first;
-    vis.capacity = capacity;
     vis.ray = (int32_t)i;
-    vis.ray_ids = ray_ids;
-    vis.t0 = t0;
-    vis.t1 = t1;
-    vis.vox = vox;
     vis.lev = 0;
-    vis.R = g.R;
-    trace_ray<kVdb, kSkip>(g, tree, o, d, lat, vis);
+    trace_ray<kVdb, kSkip>(g, tree, o, d, lat, vis, ctx);
 }
 
 __global__ void pool_reset_kernel(int32_t *head) {
@@ -223,7 +271,6 @@ Lattice make_lattice(float near_t, float far_t, const ogv_step *step, void *ws, 
     lat.tmin = near_t;
     lat.tmax = far_t;
     lat.dt = step->dt;
-    lat.inv_dt = 0.0f;   // set on the device
     lat.cone = step->kind == OGV_STEP_CONE;
     lat.tab = lat.cone ? (const float *)((char *)ws + p.off_tab) : nullptr;
     lat.n_tab = p.tab_cap;
@@ -235,6 +282,14 @@ size_t lds_bytes(const GridView &g) {
 }
 
 constexpr size_t kLdsTreeBytes = 32768;
+
+// Ray slots per lane in the refill counting kernel (0 disables it); the
+// OGV_REFILL environment variable overrides it, for measurement.
+int refill_waves_default() {
+    const char *e = std::getenv("OGV_REFILL");
+    return e ? std::max(0, std::atoi(e)) : 4;
+}
+const int g_refill_waves = refill_waves_default();
 
 struct Bufs {
     int32_t *counts, *nruns;
@@ -263,14 +318,23 @@ RunReader reader_of(const Bufs &b) {
 
 template <bool kVdb, bool kSkip, bool kLds>
 void launch_count(const GridView &g, const float *o, const float *d, int64_t n, const Lattice &lat, const Bufs &b,
-                  hipStream_t s) {
-    unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
+                  int width, hipStream_t s) {
+    unsigned blocks = (unsigned)((tiled_threads(n, width) + kBlock - 1) / kBlock);
     size_t shm = kLds ? lds_bytes(g) : 0;
     pool_reset_kernel<<<1, 64, 0, s>>>(b.pool.head);
-    if (g.L == 1)
-        count_kernel<kVdb, kSkip, kLds, true><<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool);
+    if (g.L == 1 && !kSkip && g_refill_waves > 0) {
+        const int64_t slots = tiled_threads(n, width);
+        const int per_wave = 64 * g_refill_waves;
+        const int64_t waves = (slots + per_wave - 1) / per_wave;
+        const unsigned rblocks = (unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64));
+        count_refill_kernel<kVdb, kLds>
+            <<<rblocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool, width, slots, per_wave);
+    } else if (g.L == 1)
+        count_kernel<kVdb, kSkip, kLds, true>
+            <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool, width);
     else
-        count_kernel<kVdb, kSkip, kLds, false><<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool);
+        count_kernel<kVdb, kSkip, kLds, false>
+            <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool, width);
 }
 
 template <bool kVdb, bool kSkip, bool kLds>
@@ -288,17 +352,17 @@ void launch_fill(const GridView &g, const float *o, const float *d, int64_t n, c
 }
 
 void dispatch_count(const GridView &g, int variant, const float *o, const float *d, int64_t n, const Lattice &lat,
-                    const Bufs &b, hipStream_t s) {
+                    const Bufs &b, int width, hipStream_t s) {
     const bool lds = lds_bytes(g) <= kLdsTreeBytes;
     if (g.kind == 0) {
-        if (variant == OGV_SKIP) launch_count<false, true, false>(g, o, d, n, lat, b, s);
-        else launch_count<false, false, false>(g, o, d, n, lat, b, s);
+        if (variant == OGV_SKIP) launch_count<false, true, false>(g, o, d, n, lat, b, width, s);
+        else launch_count<false, false, false>(g, o, d, n, lat, b, width, s);
     } else if (lds) {
-        if (variant == OGV_SKIP) launch_count<true, true, true>(g, o, d, n, lat, b, s);
-        else launch_count<true, false, true>(g, o, d, n, lat, b, s);
+        if (variant == OGV_SKIP) launch_count<true, true, true>(g, o, d, n, lat, b, width, s);
+        else launch_count<true, false, true>(g, o, d, n, lat, b, width, s);
     } else {
-        if (variant == OGV_SKIP) launch_count<true, true, false>(g, o, d, n, lat, b, s);
-        else launch_count<true, false, false>(g, o, d, n, lat, b, s);
+        if (variant == OGV_SKIP) launch_count<true, true, false>(g, o, d, n, lat, b, width, s);
+        else launch_count<true, false, false>(g, o, d, n, lat, b, width, s);
     }
 }
 
@@ -332,8 +396,8 @@ ogv_status build_table(float near_t, float far_t, const ogv_step *step, void *ws
 }
 
 // count + exclusive scan; offsets[n] = total; overflow (nullable) = total > capacity
-ogv_status count_and_scan(const ogv_grid *grid, int32_t variant, const float *o, const float *d, int64_t n,
-                          const Lattice &lat, int64_t *offsets, void *ws, const Plan &p, int64_t capacity,
+ogv_status count_and_scan(const ogv_grid *grid, int32_t variant, int width, const float *o, const float *d,
+                          int64_t n, const Lattice &lat, int64_t *offsets, void *ws, const Plan &p, int64_t capacity,
                           int32_t *overflow, hipStream_t s) {
     if (n == 0) {
         zero_kernel<<<1, 64, 0, s>>>(offsets, overflow);
@@ -341,7 +405,7 @@ ogv_status count_and_scan(const ogv_grid *grid, int32_t variant, const float *o,
         return OGV_OK;
     }
     Bufs b = bufs_of(ws, p);
-    dispatch_count(grid->view, variant, o, d, n, lat, b, s);
+    dispatch_count(grid->view, variant, o, d, n, lat, b, width, s);
     OGV_CHECK_LAUNCH();
     OGV_CHECK_HIP(launch_excl_scan(b.counts, n, offsets, b.tiles, capacity, overflow, s));
     return OGV_OK;
@@ -369,10 +433,12 @@ ogv_status fill_all(const ogv_grid *grid, int32_t variant, const float *o, const
     return OGV_OK;
 }
 
-ogv_status prepare(const ogv_grid *grid, int32_t variant, const float *o, const float *d, int64_t n, float near_t,
-                   float far_t, const ogv_step *step, void *ws, size_t ws_bytes, Plan *p, const char *fn) {
-    ogv_status st = validate_sampling(grid, variant, o, d, n, near_t, far_t, step, fn);
+ogv_status prepare(const ogv_grid *grid, const ogv_sample_opts &opts, const float *o, const float *d, int64_t n,
+                   float near_t, float far_t, const ogv_step *step, void *ws, size_t ws_bytes, Plan *p,
+                   const char *fn) {
+    ogv_status st = validate_sampling(grid, opts.variant, o, d, n, near_t, far_t, step, fn);
     if (st != OGV_OK) return st;
+    if (opts.image_width < 0) OGV_FAIL(OGV_ERR_INVALID, std::string(fn) + ": image_width < 0");
     std::string why;
     if (!make_plan(n, near_t, far_t, step, p, &why)) OGV_FAIL(OGV_ERR_UNSUPPORTED, why);
     if (!ws || ws_bytes < p->total)
@@ -396,40 +462,45 @@ extern "C" ogv_status ogv_sample_workspace_size(int64_t n_rays, float near_t, fl
     return OGV_OK;
 }
 
-extern "C" ogv_status ogv_sample_count(const ogv_grid *grid, int32_t variant, const float *o, const float *d,
-                                       int64_t n, float near_t, float far_t, const ogv_step *step, int64_t *offsets,
-                                       void *ws, size_t ws_bytes, void *stream) {
+static ogv_sample_opts opts_of(const ogv_sample_opts *o) { return o ? *o : ogv_sample_opts{OGV_BRANCH, 0}; }
+
+extern "C" ogv_status ogv_sample_count(const ogv_grid *grid, const ogv_sample_opts *opts_p, const float *o,
+                                       const float *d, int64_t n, float near_t, float far_t, const ogv_step *step,
+                                       int64_t *offsets, void *ws, size_t ws_bytes, void *stream) {
+    const ogv_sample_opts opts = opts_of(opts_p);
     Plan p;
-    ogv_status st = prepare(grid, variant, o, d, n, near_t, far_t, step, ws, ws_bytes, &p, "ogv_sample_count");
+    ogv_status st = prepare(grid, opts, o, d, n, near_t, far_t, step, ws, ws_bytes, &p, "ogv_sample_count");
     if (st != OGV_OK) return st;
     if (!offsets) OGV_FAIL(OGV_ERR_INVALID, "offsets is null");
     hipStream_t s = (hipStream_t)stream;
     if ((st = build_table(near_t, far_t, step, ws, p, s)) != OGV_OK) return st;
     Lattice lat = make_lattice(near_t, far_t, step, ws, p);
-    return count_and_scan(grid, variant, o, d, n, lat, offsets, ws, p, 0, nullptr, s);
+    return count_and_scan(grid, opts.variant, opts.image_width, o, d, n, lat, offsets, ws, p, 0, nullptr, s);
 }
 
-extern "C" ogv_status ogv_sample_fill(const ogv_grid *grid, int32_t variant, const float *o, const float *d,
-                                      int64_t n, float near_t, float far_t, const ogv_step *step,
+extern "C" ogv_status ogv_sample_fill(const ogv_grid *grid, const ogv_sample_opts *opts_p, const float *o,
+                                      const float *d, int64_t n, float near_t, float far_t, const ogv_step *step,
                                       const int64_t *offsets, int64_t capacity, int32_t *ray_ids, float *t0,
                                       float *t1, int32_t *vox, void *ws, size_t ws_bytes, void *stream) {
+    const ogv_sample_opts opts = opts_of(opts_p);
     Plan p;
-    ogv_status st = prepare(grid, variant, o, d, n, near_t, far_t, step, ws, ws_bytes, &p, "ogv_sample_fill");
+    ogv_status st = prepare(grid, opts, o, d, n, near_t, far_t, step, ws, ws_bytes, &p, "ogv_sample_fill");
     if (st != OGV_OK) return st;
     if (!offsets) OGV_FAIL(OGV_ERR_INVALID, "offsets is null");
     if (capacity < 0) OGV_FAIL(OGV_ERR_INVALID, "capacity < 0");
     if (capacity > 0 && (!ray_ids || !t0 || !t1)) OGV_FAIL(OGV_ERR_INVALID, "null sample array");
     hipStream_t s = (hipStream_t)stream;
     Lattice lat = make_lattice(near_t, far_t, step, ws, p);
-    return fill_all(grid, variant, o, d, n, lat, offsets, capacity, ray_ids, t0, t1, vox, ws, p, s);
+    return fill_all(grid, opts.variant, o, d, n, lat, offsets, capacity, ray_ids, t0, t1, vox, ws, p, s);
 }
 
-extern "C" ogv_status ogv_sample_rays(const ogv_grid *grid, int32_t variant, const float *o, const float *d,
-                                      int64_t n, float near_t, float far_t, const ogv_step *step, int64_t *offsets,
-                                      int64_t capacity, int32_t *ray_ids, float *t0, float *t1, int32_t *vox,
-                                      int32_t *overflow, void *ws, size_t ws_bytes, void *stream) {
+extern "C" ogv_status ogv_sample_rays(const ogv_grid *grid, const ogv_sample_opts *opts_p, const float *o,
+                                      const float *d, int64_t n, float near_t, float far_t, const ogv_step *step,
+                                      int64_t *offsets, int64_t capacity, int32_t *ray_ids, float *t0, float *t1,
+                                      int32_t *vox, int32_t *overflow, void *ws, size_t ws_bytes, void *stream) {
+    const ogv_sample_opts opts = opts_of(opts_p);
     Plan p;
-    ogv_status st = prepare(grid, variant, o, d, n, near_t, far_t, step, ws, ws_bytes, &p, "ogv_sample_rays");
+    ogv_status st = prepare(grid, opts, o, d, n, near_t, far_t, step, ws, ws_bytes, &p, "ogv_sample_rays");
     if (st != OGV_OK) return st;
     if (!offsets || !overflow) OGV_FAIL(OGV_ERR_INVALID, "offsets/overflow is null");
     if (capacity < 0) OGV_FAIL(OGV_ERR_INVALID, "capacity < 0");
@@ -437,6 +508,8 @@ extern "C" ogv_status ogv_sample_rays(const ogv_grid *grid, int32_t variant, con
     hipStream_t s = (hipStream_t)stream;
     if ((st = build_table(near_t, far_t, step, ws, p, s)) != OGV_OK) return st;
     Lattice lat = make_lattice(near_t, far_t, step, ws, p);
-    if ((st = count_and_scan(grid, variant, o, d, n, lat, offsets, ws, p, capacity, overflow, s)) != OGV_OK) return st;
-    return fill_all(grid, variant, o, d, n, lat, offsets, capacity, ray_ids, t0, t1, vox, ws, p, s);
+    if ((st = count_and_scan(grid, opts.variant, opts.image_width, o, d, n, lat, offsets, ws, p, capacity, overflow,
+                             s)) != OGV_OK)
+        return st;
+    return fill_all(grid, opts.variant, o, d, n, lat, offsets, capacity, ray_ids, t0, t1, vox, ws, p, s);
 }

@@ -230,8 +230,8 @@ struct VdbCursor {
 // kSkip = false is Alg. 1 (every cell visited, branch on occupancy);
 // kSkip = true is Alg. 2 (an inner loop passes all leading empty cells, then
 // the occupied run is marched).
-template <bool kSkip, class Cursor, class Vis>
-__device__ __forceinline__ void drive(Cursor &c, float a, float b, float tmax, Vis &vis) {
+template <bool kSkip, class Cursor, class Vis, class Ctx>
+__device__ __forceinline__ void drive(Cursor &c, float a, float b, float tmax, Vis &vis, const Ctx &ctx) {
     float lo = a;
     if (!kSkip) {
         bool in_run = false;
@@ -248,7 +248,7 @@ __device__ __forceinline__ void drive(Cursor &c, float a, float b, float tmax, V
             if (!end) end = !c.step(axis, hi);
             // a run closes at lo on an empty cell, or at this cell's end when the ray ends
             if (in_run && (!occ || end)) {
-                vis.run(run_lo, occ ? fminf(hi, b) : lo);
+                vis.run(ctx, run_lo, occ ? fminf(hi, b) : lo);
                 in_run = false;
             }
             if (end) return;
@@ -273,7 +273,7 @@ __device__ __forceinline__ void drive(Cursor &c, float a, float b, float tmax, V
                 lo = hi;
                 if (end || !c.occupied()) break;
             }
-            vis.run(run_lo, run_hi);
+            vis.run(ctx, run_lo, run_hi);
             if (end) return;
         }
     }
@@ -299,17 +299,22 @@ struct RunPool {
     int32_t cap;
 };
 
+// Uniform context of the count pass.
+struct CountCtx {
+    Lattice lat;
+    RunPool pool;
+};
+
+// Per-lane state of the count pass.
 struct CountVis {
-    const Lattice *lat;
     int32_t n;            // samples
     int32_t nr;           // runs stored (kRunsLost: pool exhausted)
     int64_t ray;
-    RunPool pool;
     int32_t chunk;        // chunk receiving runs nr.. (when nr >= kMaxRuns)
     int32_t cur0, cur1;   // run held back for merging (cur1 > cur0 when held)
 
     __device__ __forceinline__ void begin_level(int, const Axis &, const Axis &, const Axis &) {}
-    __device__ __forceinline__ void store(int32_t a, int32_t b) {
+    __device__ __forceinline__ void store(const RunPool &pool, int32_t a, int32_t b) {
         if (nr == kRunsLost) return;
         const int j = nr % kMaxRuns;
         if (nr < kMaxRuns) {
@@ -330,31 +335,29 @@ struct CountVis {
         }
         ++nr;
     }
-    __device__ __forceinline__ void run(float lo, float hi) {
-        int32_t n0 = lat->first_above(lo);
-        int32_t n1 = lat->first_above(fminf(hi, lat->tmax));
+    __device__ __forceinline__ void run(const CountCtx &x, float lo, float hi) {
+        int32_t n0 = x.lat.first_above(lo);
+        int32_t n1 = x.lat.first_above(fminf(hi, x.lat.tmax));
         if (n1 <= n0) return;
         n += n1 - n0;
         if (cur1 > cur0 && cur1 == n0) {
             cur1 = n1;
             return;
         }
-        if (cur1 > cur0) store(cur0, cur1);
+        if (cur1 > cur0) store(x.pool, cur0, cur1);
         cur0 = n0;
         cur1 = n1;
     }
-    __device__ __forceinline__ void finish() {
-        if (cur1 > cur0) store(cur0, cur1);
+    __device__ __forceinline__ void finish(const CountCtx &x) {
+        if (cur1 > cur0) store(x.pool, cur0, cur1);
     }
 };
 
-__device__ __forceinline__ CountVis make_count_vis(const Lattice *lat, int64_t ray, const RunPool &pool) {
+__device__ __forceinline__ CountVis make_count_vis(int64_t ray, const RunPool &pool) {
     CountVis v;
-    v.lat = lat;
     v.n = 0;
     v.nr = 0;
     v.ray = ray;
-    v.pool = pool;
     v.chunk = -1;
     v.cur0 = 0;
     v.cur1 = 0;
@@ -362,16 +365,23 @@ __device__ __forceinline__ CountVis make_count_vis(const Lattice *lat, int64_t r
     return v;
 }
 
-template <bool kVox>
-struct FillVis {
-    const Lattice *lat;
-    int64_t idx, capacity;
-    int32_t ray;
+// Uniform context of the traversal fill.
+struct FillCtx {
+    Lattice lat;
+    int64_t capacity;
     int32_t *ray_ids;
     float *t0, *t1;
-    int32_t *vox;       // written when kVox
-    int lev, R;
-    Axis A0, A1, A2;    // level geometry, for voxel ids only
+    int32_t *vox;         // written when kVox
+    int R;
+};
+
+// Per-lane state of the traversal fill.
+template <bool kVox>
+struct FillVis {
+    int64_t idx;
+    int32_t ray;
+    int lev;
+    Axis A0, A1, A2;      // level geometry, for voxel ids only
 
     __device__ __forceinline__ void begin_level(int l, const Axis &a0, const Axis &a1, const Axis &a2) {
         lev = l;
@@ -381,22 +391,22 @@ struct FillVis {
             A2 = a2;
         }
     }
-    __device__ __forceinline__ int vcoord(const Axis &A, float t) const {
+    __device__ __forceinline__ static int vcoord(const Axis &A, float t) {
         return A.zero ? A.zero_voxel() : A.voxel(A.locate(t, false));
     }
-    __device__ __forceinline__ void run(float lo, float hi) {
-        int n0 = lat->first_above(lo);
-        int n1 = lat->first_above(fminf(hi, lat->tmax));
-        float tn = lat->t(n0);
+    __device__ __forceinline__ void run(const FillCtx &x, float lo, float hi) {
+        int n0 = x.lat.first_above(lo);
+        int n1 = x.lat.first_above(fminf(hi, x.lat.tmax));
+        float tn = x.lat.t(n0);
         for (int n = n0; n < n1; ++n) {
-            float tnext = lat->t(n + 1);
-            if (idx < capacity) {
-                ray_ids[idx] = ray;
-                t0[idx] = tn;
-                t1[idx] = tnext;
+            float tnext = x.lat.t(n + 1);
+            if (idx < x.capacity) {
+                x.ray_ids[idx] = ray;
+                x.t0[idx] = tn;
+                x.t1[idx] = tnext;
                 if (kVox) {
                     int i = vcoord(A0, tn), j = vcoord(A1, tn), k = vcoord(A2, tn);
-                    vox[idx] = ((lev * R + i) * R + j) * R + k;
+                    x.vox[idx] = ((lev * x.R + i) * x.R + j) * x.R + k;
                 }
             }
             ++idx;
@@ -411,16 +421,26 @@ struct Ray {
     float o0, o1, o2, d0, d1, d2, r0, r1, r2;
 };
 
-template <bool kVdb, bool kSkip, class Vis>
-__device__ __forceinline__ void march_segment(const GridView &g, const Tree &tree, int lev, const Ray &ray, float a,
-                                              float b, const Lattice &lat, Vis &vis) {
+template <bool kVdb>
+struct CursorOf {
+    using type = DenseCursor;
+};
+template <>
+struct CursorOf<true> {
+    using type = VdbCursor;
+};
+
+// Puts the cursor of level `lev` on the voxel owning t_min when t_min lies
+// after the segment start a, else on the voxel owning the parameters just
+// after a.  False when that voxel is outside the grid.
+template <bool kVdb, class Vis>
+__device__ __forceinline__ bool cursor_begin(typename CursorOf<kVdb>::type &c, const GridView &g, const Tree &tree,
+                                             int lev, const Ray &ray, float a, const Lattice &lat, Vis &vis) {
     const int R = g.R;
     Axis A0 = load_axis(g.geom, lev, 0, R, ray.o0, ray.d0, ray.r0);
     Axis A1 = load_axis(g.geom, lev, 1, R, ray.o1, ray.d1, ray.r1);
     Axis A2 = load_axis(g.geom, lev, 2, R, ray.o2, ray.d2, ray.r2);
     vis.begin_level(lev, A0, A1, A2);
-    // start at the voxel owning t_min when it lies inside the segment,
-    // else at the voxel owning the parameters just after a
     const bool after = lat.tmin > a;
     const float ts = after ? lat.tmin : a;
     int u0 = A0.zero ? 0 : A0.locate(ts, !after);
@@ -429,37 +449,38 @@ __device__ __forceinline__ void march_segment(const GridView &g, const Tree &tre
     int v0 = A0.zero ? A0.zero_voxel() : A0.voxel(u0);
     int v1 = A1.zero ? A1.zero_voxel() : A1.voxel(u1);
     int v2 = A2.zero ? A2.zero_voxel() : A2.voxel(u2);
-    if ((unsigned)v0 >= (unsigned)R || (unsigned)v1 >= (unsigned)R || (unsigned)v2 >= (unsigned)R) return;
-    const float inf = __builtin_huge_valf();
-    if (!kVdb) {
-        DenseCursor c;
+    if ((unsigned)v0 >= (unsigned)R || (unsigned)v1 >= (unsigned)R || (unsigned)v2 >= (unsigned)R) return false;
+    c.R = R;
+    c.A0 = A0; c.A1 = A1; c.A2 = A2;
+    c.u0 = u0; c.u1 = u1; c.u2 = u2;
+    c.v0 = v0; c.v1 = v1; c.v2 = v2;
+    if constexpr (!kVdb) {
+        const float inf = __builtin_huge_valf();
         c.bits = g.bits;
         c.level_base = (uint64_t)lev * R * R * R;
-        c.R = R;
-        c.A0 = A0; c.A1 = A1; c.A2 = A2;
-        c.u0 = u0; c.u1 = u1; c.u2 = u2;
-        c.v0 = v0; c.v1 = v1; c.v2 = v2;
         c.tn0 = A0.zero ? inf : A0.Tk(u0 + 1);
         c.tn1 = A1.zero ? inf : A1.Tk(u1 + 1);
         c.tn2 = A2.zero ? inf : A2.Tk(u2 + 1);
-        drive<kSkip>(c, a, b, lat.tmax, vis);
     } else {
-        VdbCursor c;
         c.t = tree;
         c.lev = lev;
-        c.R = R;
         c.sh = 3 + tree.ilog2;
-        c.A0 = A0; c.A1 = A1; c.A2 = A2;
-        c.u0 = u0; c.u1 = u1; c.u2 = u2;
-        c.v0 = v0; c.v1 = v1; c.v2 = v2;
         c.k0 = c.k1 = c.k2 = 0;
         c.D = 1;
         c.lblk = -1;
         c.lbase = 0;
         c.wx = 0;
         c.word = 0;
-        drive<kSkip>(c, a, b, lat.tmax, vis);
     }
+    return true;
+}
+
+template <bool kVdb, bool kSkip, class Vis, class Ctx>
+__device__ __forceinline__ void march_segment(const GridView &g, const Tree &tree, int lev, const Ray &ray, float a,
+                                              float b, const Lattice &lat, Vis &vis, const Ctx &ctx) {
+    typename CursorOf<kVdb>::type c;
+    if (!cursor_begin<kVdb>(c, g, tree, lev, ray, a, lat, vis)) return;
+    drive<kSkip>(c, a, b, lat.tmax, vis, ctx);
 }
 
 // Level `lev` holds exactly the parameters (E, X]; false if the ray misses it.
@@ -478,9 +499,9 @@ __device__ __forceinline__ bool span_of(const GridView &g, int lev, const Ray &r
 // f+(k-m) on (X_{f+k-m-1}, X_{f+k-m}].  Each segment is marched by its level.
 // kL1: the grid has a single level (no cascades), so the level geometry is
 // uniform across the wave.
-template <bool kVdb, bool kSkip, bool kL1 = false, class Vis>
+template <bool kVdb, bool kSkip, bool kL1 = false, class Vis, class Ctx>
 __device__ __forceinline__ void trace_ray(const GridView &g, const Tree &tree, const float o[3], const float d[3],
-                                          const Lattice &lat, Vis &vis) {
+                                          const Lattice &lat, Vis &vis, const Ctx &ctx) {
     if (!(lat.tmin <= lat.tmax)) return;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -489,7 +510,7 @@ __device__ __forceinline__ void trace_ray(const GridView &g, const Tree &tree, c
     if (kL1) {
         float E, X;
         if (span_of(g, 0, ray, E, X) && E < lat.tmax && X >= lat.tmin)
-            march_segment<kVdb, kSkip>(g, tree, 0, ray, E, X, lat, vis);
+            march_segment<kVdb, kSkip>(g, tree, 0, ray, E, X, lat, vis, ctx);
         return;
     }
     const int L = g.L;
@@ -528,8 +549,59 @@ __device__ __forceinline__ void trace_ray(const GridView &g, const Tree &tree, c
         float a = k <= m ? E_l : X_i;
         float b = k < m ? E_i : X_l;
         if (a >= lat.tmax) break;   // this and every later segment lie past t_max
-        if (a < b && b >= lat.tmin) march_segment<kVdb, kSkip>(g, tree, lev, ray, a, b, lat, vis);
+        if (a < b && b >= lat.tmin) march_segment<kVdb, kSkip>(g, tree, lev, ray, a, b, lat, vis, ctx);
     }
+}
+
+// ------------------------------------------------------------------ resumable walk
+
+// A single-level ray walk in Alg. 1 form that advances one cell per call, so
+// a lane can drop a finished ray and take the next one (lane refill) instead
+// of idling until the slowest ray of its wave ends.
+template <bool kVdb>
+struct Walk {
+    typename CursorOf<kVdb>::type c;
+    float lo, b, run_lo;
+    bool in_run;
+};
+
+// false when the ray has nothing to walk
+template <bool kVdb, class Vis>
+__device__ __forceinline__ bool walk_begin(Walk<kVdb> &w, const GridView &g, const Tree &tree, const float o[3],
+                                           const float d[3], const Lattice &lat, Vis &vis) {
+    if (!(lat.tmin <= lat.tmax)) return false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (!__builtin_isfinite(o[a]) || !__builtin_isfinite(d[a])) return false;
+    Ray ray{o[0], o[1], o[2], d[0], d[1], d[2], __fdiv_rn(1.0f, d[0]), __fdiv_rn(1.0f, d[1]), __fdiv_rn(1.0f, d[2])};
+    float E, X;
+    if (!span_of(g, 0, ray, E, X) || !(E < lat.tmax) || !(X >= lat.tmin) || !(E < X)) return false;
+    if (!cursor_begin<kVdb>(w.c, g, tree, 0, ray, E, lat, vis)) return false;
+    w.lo = E;
+    w.b = X;
+    w.in_run = false;
+    w.run_lo = E;
+    return true;
+}
+
+// one cell; true when the ray is finished
+template <bool kVdb, class Vis, class Ctx>
+__device__ __forceinline__ bool walk_step(Walk<kVdb> &w, float tmax, Vis &vis, const Ctx &ctx) {
+    const bool occ = w.c.occupied();
+    int axis;
+    const float hi = w.c.exit(axis);
+    if (occ && !w.in_run) {
+        w.in_run = true;
+        w.run_lo = w.lo;
+    }
+    bool end = hi >= w.b || hi >= tmax;
+    if (!end) end = !w.c.step(axis, hi);
+    if (w.in_run && (!occ || end)) {
+        vis.run(ctx, w.run_lo, occ ? fminf(hi, w.b) : w.lo);
+        w.in_run = false;
+    }
+    w.lo = hi;
+    return end;
 }
 
 // ------------------------------------------------------------------ expansion fill
@@ -673,6 +745,30 @@ __device__ __forceinline__ void expand_block(const int64_t *__restrict__ offsets
         }
         __syncthreads();
     }
+}
+
+// ------------------------------------------------------------------ ray order
+
+// Threads per image-tiled launch: 8x8-pixel tiles of 64 lanes (one wave).
+__host__ __device__ inline int64_t tiled_threads(int64_t n, int width) {
+    if (width <= 0) return n;
+    const int64_t rows = (n + width - 1) / width;
+    return ((width + 7) / 8) * ((rows + 7) / 8) * (int64_t)64;
+}
+
+// Ray walked by thread t: t itself, or with an image of `width` pixels per
+// row, lane l of wave w takes pixel (8*(w % tiles_x) + l % 8, 8*(w / tiles_x)
+// + l / 8) of the row-major image; -1 for a lane past the image.
+__device__ __forceinline__ int64_t ray_of_thread(int64_t t, int64_t n, int width) {
+    if (width <= 0) return t < n ? t : -1;
+    const int64_t w = t >> 6;
+    const int l = (int)(t & 63);
+    const int64_t tiles_x = (width + 7) >> 3;
+    const int64_t px = (w % tiles_x) * 8 + (l & 7);
+    const int64_t py = (w / tiles_x) * 8 + (l >> 3);
+    if (px >= width) return -1;
+    const int64_t r = py * width + px;
+    return r < n ? r : -1;
 }
 
 // ------------------------------------------------------------------ ray loads

@@ -15,12 +15,13 @@ from paper_2404_10272_amd import api, scenes
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_scenes(ws, kind="vdb"):
+def _gpu_scenes(ws, kind="vdb", tiled=True):
     out = []
     for w in ws:
         occ = torch.from_numpy(w.occ).cuda()
         g = api.build_vdb(occ, w.boxes, w.ilog2) if kind == "vdb" else api.build_dense(occ, w.boxes)
-        out.append((g, torch.from_numpy(w.origins).cuda(), torch.from_numpy(w.dirs).cuda(), w.near, w.far, w.step))
+        out.append((g, torch.from_numpy(w.origins).cuda(), torch.from_numpy(w.dirs).cuda(), w.near, w.far, w.step,
+                    w.image[0] if tiled else 0))
     return out
 
 
@@ -93,6 +94,9 @@ def test_graph_replays_match_eager_and_tunes_agree():
     fixed = api.Batch(gs, "branch", tune=(4096, 8))
     other, _ = _run(fixed)
     _same(other, eager, "fixed tune, branch variant")
+    untiled = api.Batch(_gpu_scenes(ws, tiled=False), "skip", tune=(512, 2))
+    other, _ = _run(untiled)
+    _same(other, eager, "no image tiling")
 
 
 def test_full_batch_matches_single_scene_calls():
@@ -103,7 +107,7 @@ def test_full_batch_matches_single_scene_calls():
     res, _ = _run(batch)
     base = batch.info()["ray_base"]
     rng = np.random.default_rng(5)
-    for s, (w, (g, o, d, near, far, step)) in enumerate(zip(ws, gs)):
+    for s, (w, (g, o, d, near, far, step, width)) in enumerate(zip(ws, gs)):
         one = api.sample_rays(g, o, d, near, far, api.make_step(step), "skip")
         one = {k: v.cpu().numpy() for k, v in one.items()}
         _same(_split(res, base, w.n_rays, s), one, f"scene {s}")

@@ -27,10 +27,10 @@ def gpu_grid(kind, occ, boxes, ilog2):
     return api.build_vdb(occ_d, boxes, ilog2)
 
 
-def gpu_sample(grid, o, d, near, far, step, variant, voxel_ids=True):
+def gpu_sample(grid, o, d, near, far, step, variant, voxel_ids=True, image_width=0):
     out = api.sample_rays(grid, torch.from_numpy(np.ascontiguousarray(o)).cuda(),
                           torch.from_numpy(np.ascontiguousarray(d)).cuda(), near, far, api.make_step(step),
-                          variant, voxel_ids=voxel_ids)
+                          variant, voxel_ids=voxel_ids, image_width=image_width)
     torch.cuda.synchronize()
     return {k: v.cpu().numpy() for k, v in out.items()}
 
@@ -181,6 +181,11 @@ def test_object_workload_800x800(obj, obj_ref, variant):
     assert_same(got, obj_ref, f"object {variant}")
     got = gpu_sample(g, obj.origins, obj.dirs, obj.near, obj.far, obj.step, variant[1], voxel_ids=False)
     assert_same(got, obj_ref, f"object {variant} (no voxel ids)")
+    # lanes on 8x8 pixel tiles: only which lane walks which ray changes
+    for width in (800, 777):
+        got = gpu_sample(g, obj.origins, obj.dirs, obj.near, obj.far, obj.step, variant[1], voxel_ids=False,
+                         image_width=width)
+        assert_same(got, obj_ref, f"object {variant} (image width {width})")
 
 
 def test_object_workload_capacity_mode(obj, obj_ref):
@@ -190,7 +195,7 @@ def test_object_workload_capacity_mode(obj, obj_ref):
     o = torch.from_numpy(obj.origins).cuda()
     d = torch.from_numpy(obj.dirs).cuda()
     S = int(obj_ref["offsets"][-1])
-    sp = api.Sampler(g, obj.n_rays, obj.near, obj.far, obj.step, "skip")
+    sp = api.Sampler(g, obj.n_rays, obj.near, obj.far, obj.step, "branch", image_width=800)
     for cap in (S, S // 3):
         ids = torch.full((cap + 16,), -7, dtype=torch.int32, device="cuda")
         t0 = torch.zeros(cap + 16, device="cuda")
