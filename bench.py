@@ -37,7 +37,7 @@ def parse():
     p.add_argument("--cpu-stride", type=int, default=4, help="oracle baseline uses every k-th ray")
     p.add_argument("--no-side", action="store_true", help="skip the composite and batched side measurements")
     p.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
-                   help="only run a plain device copy of MIB MiB (3 times), to calibrate HBM byte counters")
+                   help="first run a plain device copy of MIB MiB (3 times), to calibrate HBM byte counters")
     return p.parse_args()
 
 
@@ -70,21 +70,27 @@ class Timed:
         self.t1 = torch.empty(self.S, dtype=torch.float32, device="cuda")
 
     def step(self, ev=None):
+        # count = walk (pool reset + count kernel) then scan; fill = expansion
+        # (+ the traversal fill of lost rays, an empty launch when none are)
         if ev is not None:
             ev[0].record()
-        self.sp.count(self.o, self.d)
+        self.sp.count_raw(self.o, self.d)
         if ev is not None:
             ev[1].record()
-        self.sp.fill(self.o, self.d, self.ids, self.t0, self.t1)
+        self.sp.scan()
         if ev is not None:
             ev[2].record()
+        self.sp.fill(self.o, self.d, self.ids, self.t0, self.t1)
+        if ev is not None:
+            ev[3].record()
 
     def run(self, steps, warmup):
+        """(ms per step, walk ms, scan ms, fill ms), events on the current stream."""
         torch = self.torch
         for _ in range(warmup):
             self.step()
         torch.cuda.synchronize()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
         start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         start.record()
@@ -93,9 +99,8 @@ class Timed:
         end.record()
         torch.cuda.synchronize()
         total_ms = start.elapsed_time(end)
-        count_ms = [e[0].elapsed_time(e[1]) for e in evs]
-        fill_ms = [e[1].elapsed_time(e[2]) for e in evs]
-        return total_ms / steps, sum(count_ms) / steps, sum(fill_ms) / steps
+        stage = [sum(e[i].elapsed_time(e[i + 1]) for e in evs) / steps for i in range(3)]
+        return total_ms / steps, stage[0], stage[1], stage[2]
 
 
 def time_events(torch, fn, steps, warmup):
@@ -202,7 +207,6 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calib:
         copy_calibration(args.copy_calib)
-        return
     w = scenes.workload("object")
     occ = torch.from_numpy(w.occ).cuda()
     o = torch.from_numpy(w.origins).cuda()
@@ -231,12 +235,13 @@ def main():
     plain_skip = Timed(api, torch, dense, w, o, d, "skip", W)
     plain_rows = Timed(api, torch, dense, w, o, d, "branch", 0)
     assert hdda.S == plain.S == hdda_other.S == plain_skip.S, "samplers disagree on the sample count"
-    ms, count_ms, fill_ms = hdda.run(args.steps, args.warmup)
-    oms, ocount_ms, ofill_ms = hdda_other.run(args.steps, args.warmup)
-    rms, _, _ = hdda_rows.run(args.steps, args.warmup)
-    dms, dcount_ms, dfill_ms = plain.run(args.steps, args.warmup)
-    dsms, dscount_ms, dsfill_ms = plain_skip.run(args.steps, args.warmup)
-    drms, _, _ = plain_rows.run(args.steps, args.warmup)
+    ms, walk_ms, scan_ms, fill_ms = hdda.run(args.steps, args.warmup)
+    oms, owalk_ms, oscan_ms, ofill_ms = hdda_other.run(args.steps, args.warmup)
+    rms = hdda_rows.run(args.steps, args.warmup)[0]
+    dms, dwalk_ms, dscan_ms, dfill_ms = plain.run(args.steps, args.warmup)
+    dsms, dswalk_ms, dsscan_ms, dsfill_ms = plain_skip.run(args.steps, args.warmup)
+    drms = plain_rows.run(args.steps, args.warmup)[0]
+    count_ms = walk_ms + scan_ms
     N, S = w.n_rays, hdda.S
     G = vinfo["bytes"]
     # maximal lattice-contiguous runs (what the count kernel stores), from the
@@ -244,13 +249,15 @@ def main():
     ids, t0, t1 = hdda.ids, hdda.t0, hdda.t1
     runs = int(1 + ((ids[1:] != ids[:-1]) | (t0[1:] != t1[:-1])).sum().item()) if S > 0 else 0
     # algorithmic bytes per launch
-    count_bytes = 24 * N + 12 * N + 8 * runs + G          # rays read; counts, run counts, chain heads, runs written
+    walk_bytes = 24 * N + 12 * N + 8 * runs + G           # rays and grid read; counts, run counts, chain heads, runs
     fill_bytes = 8 * N + 4 * N + 8 * runs + 12 * S        # offsets, run counts, runs read; samples written
     step_bytes = 24 * N + 8 * (N + 1) + 12 * S + G        # the call's inputs and outputs
-    if count_ms >= fill_ms:
-        dom = {"kernel": "count_kernel<vdb> + scan", "bytes": count_bytes, "ms": count_ms}
+    if walk_ms >= fill_ms:
+        dom = {"kernel": "count_kernel", "stage": "walk: pool reset + count_kernel (VDB, hierarchical DDA)",
+               "bytes": walk_bytes, "ms": walk_ms}
     else:
-        dom = {"kernel": "expand_kernel (+ fallback fill)", "bytes": fill_bytes, "ms": fill_ms}
+        dom = {"kernel": "expand_kernel", "stage": "fill: expand_kernel + lost-ray traversal fill (empty launch)",
+               "bytes": fill_bytes, "ms": fill_ms}
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
 
     traffic = None
@@ -281,28 +288,30 @@ def main():
                                "near 2, far 6, step 5e-3; VDB internal nodes 16^3 over 8^3 leaves",
                    "rays": N, "samples": S, "variant": args.variant, "lanes": "8x8 pixel tiles"},
         "samples_per_s": S / (ms * 1e-3),
-        "vdb": {"ms_per_step": ms, "count_scan_ms": count_ms, "fill_ms": fill_ms, "rays_per_s": N / (ms * 1e-3),
+        "vdb": {"ms_per_step": ms, "count_scan_ms": count_ms, "walk_ms": walk_ms, "scan_ms": scan_ms,
+                "fill_ms": fill_ms, "rays_per_s": N / (ms * 1e-3),
                 "bytes": G, "leaves": vinfo["n_leaves"], "build_ms": build_ms},
-        "vdb_" + other: {"ms_per_step": oms, "count_scan_ms": ocount_ms, "fill_ms": ofill_ms,
+        "vdb_" + other: {"ms_per_step": oms, "count_scan_ms": owalk_ms + oscan_ms, "walk_ms": owalk_ms,
+                         "fill_ms": ofill_ms,
                          "rays_per_s": N / (oms * 1e-3)},
         "vdb_row_major_lanes": {"ms_per_step": rms, "rays_per_s": N / (rms * 1e-3)},
         "dense_row_major_lanes": {"ms_per_step": drms, "rays_per_s": N / (drms * 1e-3)},
-        "dense": {"ms_per_step": dms, "count_scan_ms": dcount_ms, "fill_ms": dfill_ms,
+        "dense": {"ms_per_step": dms, "count_scan_ms": dwalk_ms + dscan_ms, "walk_ms": dwalk_ms,
+                  "fill_ms": dfill_ms,
                   "rays_per_s": N / (dms * 1e-3), "samples_per_s": S / (dms * 1e-3), "bytes": dinfo["bytes"],
                   "variant": "branch"},
-        "dense_skip": {"ms_per_step": dsms, "count_scan_ms": dscount_ms, "fill_ms": dsfill_ms,
+        "dense_skip": {"ms_per_step": dsms, "count_scan_ms": dswalk_ms + dsscan_ms, "walk_ms": dswalk_ms,
+                       "fill_ms": dsfill_ms,
                        "rays_per_s": N / (dsms * 1e-3)},
         "speedup_vs_dense": dms / ms,
         "step_bytes": step_bytes,
         "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "runs": runs,
-        "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+        "roofline": {"bound": "hbm", "kernel": dom["kernel"], "stage": dom["stage"], "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes": dom["bytes"], "avg_ms": dom["ms"],
-                     "other_stage": {"kernel": "expand_kernel (+ fallback fill)" if dom["ms"] == count_ms
-                                     else "count_kernel<vdb> + scan",
-                                     "algorithmic_bytes": fill_bytes if dom["ms"] == count_ms else count_bytes,
-                                     "avg_ms": fill_ms if dom["ms"] == count_ms else count_ms}},
+                     "stages_ms": {"walk": walk_ms, "scan": scan_ms, "fill": fill_ms},
+                     "stage_bytes": {"walk": walk_bytes, "scan": 4 * N + 8 * (N + 1), "fill": fill_bytes}},
     }
     if not args.no_side:
         line["composite"] = composite_side(api, torch, scenes, hdda, N, min(args.steps, 20))

@@ -145,6 +145,17 @@ ogv_status ogv_sample_count(const ogv_grid *grid, const ogv_sample_opts *opts, c
                             int64_t n_rays, float near_t, float far_t, const ogv_step *step_host,
                             int64_t *offsets_dev, void *ws_dev, size_t ws_bytes, void *stream);
 
+/* The two halves of ogv_sample_count, for callers that time or schedule
+ * them apart: ogv_sample_count_raw walks the rays and leaves the per-ray
+ * counts and runs in the workspace (same arguments as ogv_sample_count,
+ * without offsets); ogv_sample_scan then writes offsets_dev (int64
+ * [n_rays + 1]) from those counts.  n_rays must equal the count call's, and
+ * ws_bytes must be at least that call's workspace size. */
+ogv_status ogv_sample_count_raw(const ogv_grid *grid, const ogv_sample_opts *opts, const float *origins_dev,
+                                const float *dirs_dev, int64_t n_rays, float near_t, float far_t,
+                                const ogv_step *step_host, void *ws_dev, size_t ws_bytes, void *stream);
+ogv_status ogv_sample_scan(int64_t n_rays, int64_t *offsets_dev, void *ws_dev, size_t ws_bytes, void *stream);
+
 /* Emission pass: writes ray i's samples at offsets[i] .. offsets[i+1]-1.
  *   offsets_dev       from ogv_sample_count with the same arguments.
  *   ws_dev            the workspace that ogv_sample_count filled, unchanged

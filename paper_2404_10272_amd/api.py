@@ -65,6 +65,9 @@ SIGNATURES = {
     "ogv_sample_workspace_size": (I32, [I64, F32, F32, ctypes.POINTER(_Step), ctypes.POINTER(SZ)]),
     "ogv_sample_count": (I32, [VP, ctypes.POINTER(_Opts), VP, VP, I64, F32, F32, ctypes.POINTER(_Step), VP, VP, SZ,
                                VP]),
+    "ogv_sample_count_raw": (I32, [VP, ctypes.POINTER(_Opts), VP, VP, I64, F32, F32, ctypes.POINTER(_Step), VP, SZ,
+                                   VP]),
+    "ogv_sample_scan": (I32, [I64, VP, VP, SZ, VP]),
     "ogv_sample_fill": (I32, [VP, ctypes.POINTER(_Opts), VP, VP, I64, F32, F32, ctypes.POINTER(_Step), VP, I64, VP, VP,
                               VP, VP, VP, SZ, VP]),
     "ogv_sample_rays": (I32, [VP, ctypes.POINTER(_Opts), VP, VP, I64, F32, F32, ctypes.POINTER(_Step), VP, I64, VP, VP,
@@ -221,6 +224,17 @@ class Sampler:
         _check(lib().ogv_sample_count(self.grid.handle, ctypes.byref(self.opts), _ptr(o), _ptr(d), self.n, self.near, self.far,
                                       ctypes.byref(self.step), _ptr(self.offsets), _ptr(self.ws), self.ws_bytes,
                                       _stream(stream)))
+        return self.offsets
+
+    def count_raw(self, o, d, stream=None):
+        """The walk half of count(): counts and runs stay in the workspace."""
+        _check(lib().ogv_sample_count_raw(self.grid.handle, ctypes.byref(self.opts), _ptr(o), _ptr(d), self.n,
+                                          self.near, self.far, ctypes.byref(self.step), _ptr(self.ws), self.ws_bytes,
+                                          _stream(stream)))
+
+    def scan(self, stream=None):
+        """The scan half of count(): offsets from the counts count_raw() left."""
+        _check(lib().ogv_sample_scan(self.n, _ptr(self.offsets), _ptr(self.ws), self.ws_bytes, _stream(stream)))
         return self.offsets
 
     def fill(self, o, d, ray_ids, t0, t1, voxel_ids=None, stream=None):

@@ -40,11 +40,13 @@ struct SceneDesc {
     int32_t width;   // image width for 8x8 tiling, 0 for none
 };
 
-// zeroes the queue head and the run-pool head (queue[0], queue[1])
+// zeroes the queue head, the run-pool head and the lost-ray count
+// (queue[0], queue[1], queue[2])
 __global__ void batch_reset_kernel(int32_t *queue) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         queue[0] = 0;
         queue[1] = 0;
+        queue[2] = 0;
     }
 }
 
@@ -102,35 +104,34 @@ __global__ void __launch_bounds__(kBlock) batch_expand_kernel(const int64_t *__r
                                                               const Lattice *__restrict__ lats,
                                                               const int64_t *__restrict__ first, int n_scenes,
                                                               int64_t capacity, int32_t *__restrict__ ray_ids,
-                                                              float *__restrict__ t0, float *__restrict__ t1, int vec4) {
-    expand_block(offsets, n_total, nruns, rd, SceneLattices{lats, first, n_scenes}, capacity, ray_ids, t0, t1,
-                 vec4 != 0);
+                                                              float *__restrict__ t0, float *__restrict__ t1) {
+    expand_wave(offsets, n_total, nruns, rd, SceneLattices{lats, first, n_scenes}, capacity, ray_ids, t0, t1);
 }
 
 template <bool kSkip>
 __global__ void __launch_bounds__(kBlock) batch_overflow_fill_kernel(
-    const SceneDesc *__restrict__ scenes, int n_scenes, int64_t n_total, const int32_t *__restrict__ nruns,
-    const int64_t *__restrict__ offsets, int64_t capacity, int32_t *__restrict__ ray_ids, float *__restrict__ t0,
-    float *__restrict__ t1) {
-    const int64_t gr = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool mine = gr < n_total && nruns[gr] == kRunsLost;
-    if (!__syncthreads_or(mine)) return;
-    if (!mine) return;
-    const int64_t first_out = offsets[gr];
-    if (first_out >= capacity) return;
-    const SceneDesc *sc = scenes + scene_of_ray(scenes, n_scenes, gr);
-    const Lattice lat = sc->lat;
-    const GridView g = sc->g;
-    const Tree tree = load_tree<false>(g, nullptr);
-    float o[3], d[3];
-    load_ray(sc->o, sc->d, gr - sc->first, o, d);
-    const FillCtx ctx{lat, capacity, ray_ids, t0, t1, nullptr, g.R};
-    FillVis<false> vis;
-    vis.idx = first_out;
-    vis.ray = (int32_t)gr;
-    vis.lev = 0;
-    if (g.kind == 1) trace_ray<true, kSkip>(g, tree, o, d, lat, vis, ctx);
-    else trace_ray<false, kSkip>(g, tree, o, d, lat, vis, ctx);
+    const SceneDesc *__restrict__ scenes, int n_scenes, const int32_t *__restrict__ lost,
+    const int32_t *__restrict__ n_lost, const int64_t *__restrict__ offsets, int64_t capacity,
+    int32_t *__restrict__ ray_ids, float *__restrict__ t0, float *__restrict__ t1) {
+    const int64_t m = *n_lost;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < m; k += (int64_t)gridDim.x * kBlock) {
+        const int64_t gr = lost[k];
+        const int64_t first_out = offsets[gr];
+        if (first_out >= capacity) continue;
+        const SceneDesc *sc = scenes + scene_of_ray(scenes, n_scenes, gr);
+        const Lattice lat = sc->lat;
+        const GridView g = sc->g;
+        const Tree tree = load_tree<false>(g, nullptr);
+        float o[3], d[3];
+        load_ray(sc->o, sc->d, gr - sc->first, o, d);
+        const FillCtx ctx{lat, capacity, ray_ids, t0, t1, nullptr, g.R};
+        FillVis<false> vis;
+        vis.idx = first_out;
+        vis.ray = (int32_t)gr;
+        vis.lev = 0;
+        if (g.kind == 1) trace_ray<true, kSkip>(g, tree, o, d, lat, vis, ctx);
+        else trace_ray<false, kSkip>(g, tree, o, d, lat, vis, ctx);
+    }
 }
 
 // growing-step lattice of one scene (one thread), padded past its length
@@ -213,16 +214,17 @@ hipError_t enqueue_pass(ogv_batch *b, int64_t *offsets, int64_t capacity, int32_
     e = launch_excl_scan(b->counts, b->n_total, offsets, b->tiles, capacity, overflow, s);
     if (e != hipSuccess || capacity == 0) return e;
     unsigned blocks = (unsigned)((b->n_total + kBlock - 1) / kBlock);
-    const int vec4 = (((uintptr_t)ids | (uintptr_t)t0 | (uintptr_t)t1) & 15) == 0;
     const RunReader rd{b->pool.slots, b->pool.ray_next, b->pool.chunks, b->pool.chunk_next};
     batch_expand_kernel<<<blocks, kBlock, 0, s>>>(offsets, b->n_total, b->nruns, rd, b->lats_dev, b->first_dev,
-                                                  b->n_scenes, capacity, ids, t0, t1, vec4);
+                                                  b->n_scenes, capacity, ids, t0, t1);
+    // rays whose runs were lost (rare): a small grid strides through their list
+    const unsigned lblocks = std::min(blocks, 64u);
     if (b->variant == OGV_SKIP)
-        batch_overflow_fill_kernel<true><<<blocks, kBlock, 0, s>>>(b->desc_dev, b->n_scenes, b->n_total, b->nruns,
-                                                                   offsets, capacity, ids, t0, t1);
+        batch_overflow_fill_kernel<true><<<lblocks, kBlock, 0, s>>>(b->desc_dev, b->n_scenes, b->pool.lost,
+                                                                    b->pool.n_lost, offsets, capacity, ids, t0, t1);
     else
-        batch_overflow_fill_kernel<false><<<blocks, kBlock, 0, s>>>(b->desc_dev, b->n_scenes, b->n_total, b->nruns,
-                                                                    offsets, capacity, ids, t0, t1);
+        batch_overflow_fill_kernel<false><<<lblocks, kBlock, 0, s>>>(b->desc_dev, b->n_scenes, b->pool.lost,
+                                                                     b->pool.n_lost, offsets, capacity, ids, t0, t1);
     return hipGetLastError();
 }
 
@@ -327,6 +329,7 @@ extern "C" ogv_status ogv_batch_create(const ogv_scene *scenes, int32_t n, int32
     const int32_t pool_cap = (int32_t)std::min<int64_t>(std::max<int64_t>(256, total / 16), 1 << 24);
     size_t o_chunks = take(sizeof(int2) * (size_t)pool_cap * kMaxRuns);
     size_t o_cnext = take(sizeof(int32_t) * (size_t)pool_cap);
+    size_t o_lost = take(sizeof(int32_t) * (size_t)total);
     size_t o_tiles = take(sizeof(int64_t) * (size_t)(b->n_tiles + 1));
     size_t o_tabs = take(sizeof(float) * tab_words);
     if (hipMalloc(&b->mem, off) != hipSuccess) {
@@ -347,6 +350,8 @@ extern "C" ogv_status ogv_batch_create(const ogv_scene *scenes, int32_t n, int32
     b->pool.chunk_next = (int32_t *)(m + o_cnext);
     b->pool.head = b->queue + 1;
     b->pool.cap = pool_cap;
+    b->pool.lost = (int32_t *)(m + o_lost);
+    b->pool.n_lost = b->queue + 2;
     b->tiles = (int64_t *)(m + o_tiles);
     float *tabs = (float *)(m + o_tabs);
     std::vector<Lattice> lats(n);

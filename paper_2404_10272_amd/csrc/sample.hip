@@ -47,97 +47,49 @@ __global__ void __launch_bounds__(kBlock) count_kernel(GridView g, const float *
     nruns[i] = vis.nr;
 }
 
-// Counting with lane refill (single-level grids, Alg. 1 loop): wave w owns
-// ray slots [w*per_wave, (w+1)*per_wave) in tile order; whenever lanes are
-// idle they take the next slots, ranked by a ballot, so the wave keeps
-// stepping full until its slots run out.
-template <bool kVdb, bool kLds>
-__global__ void __launch_bounds__(kBlock) count_refill_kernel(GridView g, const float *__restrict__ origins,
-                                                              const float *__restrict__ dirs, int64_t n_rays,
-                                                              Lattice lat, int32_t *__restrict__ counts,
-                                                              int32_t *__restrict__ nruns, RunPool pool,
-                                                              int image_width, int64_t n_slots, int per_wave) {
-    extern __shared__ uint64_t smem[];
-    Tree tree = kVdb ? load_tree<kLds>(g, smem) : Tree{};
-    const CountCtx ctx{lat, pool};
-    const int lane = threadIdx.x & 63;
-    const uint64_t below = (1ull << lane) - 1ull;
-    const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    const int64_t last = min((wave + 1) * (int64_t)per_wave, n_slots);
-    int64_t next = wave * (int64_t)per_wave;
-    Walk<kVdb> w;
-    CountVis vis;
-    int64_t ray = -1;
-    bool active = false;
-    while (true) {
-        const uint64_t idle = __ballot(!active);
-        if (idle != 0 && next < last) {
-            if (!active) {
-                const int64_t slot = next + __popcll(idle & below);
-                ray = slot < last ? ray_of_thread(slot, n_rays, image_width) : -1;
-                if (ray >= 0) {
-                    float o[3], d[3];
-                    load_ray(origins, dirs, ray, o, d);
-                    vis = make_count_vis(ray, pool);
-                    active = walk_begin(w, g, tree, o, d, lat, vis);
-                    if (!active) {
-                        counts[ray] = 0;
-                        nruns[ray] = 0;
-                    }
-                }
-            }
-            next += __popcll(idle);
-        }
-        if (__ballot(active) == 0) {
-            if (next >= last) break;
-            continue;
-        }
-        if (active && walk_step(w, lat.tmax, vis, ctx)) {
-            vis.finish(ctx);
-            counts[ray] = vis.n;
-            nruns[ray] = vis.nr;
-            active = false;
-        }
-    }
-}
-
-// Traversal fill: re-walks ray i and writes its samples from offsets[i].
-// With only_lost it writes just the rays whose runs the count pass could not
-// keep; otherwise every ray (used when voxel ids are requested).
+// Traversal fill: re-walks rays and writes their samples from offsets[i]:
+// every ray (list == nullptr; used when voxel ids are requested), or the
+// *list_len rays of `list` (the rays whose runs the count pass could not
+// keep), over a grid that strides through the list.
 template <bool kVdb, bool kSkip, bool kVox, bool kLds>
 __global__ void __launch_bounds__(kBlock) fill_kernel(GridView g, const float *__restrict__ origins,
                                                       const float *__restrict__ dirs, int64_t n_rays, Lattice lat,
                                                       const int64_t *__restrict__ offsets, int64_t capacity,
                                                       int32_t *__restrict__ ray_ids, float *__restrict__ t0,
                                                       float *__restrict__ t1, int32_t *__restrict__ vox,
-                                                      const int32_t *__restrict__ only_lost) {
+                                                      const int32_t *__restrict__ list,
+                                                      const int32_t *__restrict__ list_len) {
     extern __shared__ uint64_t smem[];
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    bool mine = i < n_rays && (only_lost == nullptr || only_lost[i] == kRunsLost);
-    if (!__syncthreads_or(mine)) return;   // whole block idle: skip the staging too
+    const int64_t m = list ? (int64_t)*list_len : n_rays;
+    if ((int64_t)blockIdx.x * kBlock >= m) return;   // block-uniform: no work, skip the staging too
     Tree tree = kVdb ? load_tree<kLds>(g, smem) : Tree{};
-    if (!mine) return;
-    int64_t first = offsets[i];
-    if (first >= capacity) return;
-    float o[3], d[3];
-    load_ray(origins, dirs, i, o, d);
     const FillCtx ctx{lat, capacity, ray_ids, t0, t1, vox, g.R};
-    FillVis<kVox> vis;
-    vis.idx = first;
-    vis.ray = (int32_t)i;
-    vis.lev = 0;
-    trace_ray<kVdb, kSkip>(g, tree, o, d, lat, vis, ctx);
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < m; k += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = list ? (int64_t)list[k] : k;
+        const int64_t first = offsets[i];
+        if (first >= capacity) continue;
+        float o[3], d[3];
+        load_ray(origins, dirs, i, o, d);
+        FillVis<kVox> vis;
+        vis.idx = first;
+        vis.ray = (int32_t)i;
+        vis.lev = 0;
+        trace_ray<kVdb, kSkip>(g, tree, o, d, lat, vis, ctx);
+    }
 }
 
+// zeroes the pool head and the lost-ray count (head[0], head[1])
 __global__ void pool_reset_kernel(int32_t *head) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *head = 0;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        head[0] = 0;
+        head[1] = 0;
+    }
 }
-
 __global__ void __launch_bounds__(kBlock) expand_kernel(const int64_t *__restrict__ offsets, int64_t n_rays,
                                                         const int32_t *__restrict__ nruns, RunReader rd, Lattice lat,
                                                         int64_t capacity, int32_t *__restrict__ ray_ids,
-                                                        float *__restrict__ t0, float *__restrict__ t1, int vec4) {
-    expand_block(offsets, n_rays, nruns, rd, OneLattice{lat}, capacity, ray_ids, t0, t1, vec4 != 0);
+                                                        float *__restrict__ t0, float *__restrict__ t1) {
+    expand_wave(offsets, n_rays, nruns, rd, OneLattice{lat}, capacity, ray_ids, t0, t1);
 }
 
 // Growing-step lattice, one thread: t_0 = near, t_{k+1} = fl(t_k +
@@ -232,7 +184,8 @@ namespace {
 
 struct Plan {
     int64_t n_rays;
-    size_t off_counts, off_nruns, off_runs, off_next, off_chunks, off_cnext, off_tiles, off_tab, off_ntab, total;
+    size_t off_counts, off_nruns, off_runs, off_next, off_chunks, off_cnext, off_lost, off_tiles, off_tab, off_ntab,
+        total;
     int32_t pool_cap;
     int64_t n_tiles;
     int32_t tab_cap;
@@ -259,6 +212,7 @@ bool make_plan(int64_t n_rays, float near_t, float far_t, const ogv_step *step, 
     p->pool_cap = (int32_t)std::min<int64_t>(std::max<int64_t>(256, n_rays / 16), 1 << 24);
     p->off_chunks = take(sizeof(int2) * (size_t)p->pool_cap * kMaxRuns);
     p->off_cnext = take(sizeof(int32_t) * (size_t)p->pool_cap);
+    p->off_lost = take(sizeof(int32_t) * (size_t)n_rays);
     p->off_tiles = take(sizeof(int64_t) * (size_t)(p->n_tiles + 1));
     p->off_tab = take(sizeof(float) * (size_t)p->tab_cap);
     p->off_ntab = take(sizeof(int32_t) * 4);
@@ -283,13 +237,6 @@ size_t lds_bytes(const GridView &g) {
 
 constexpr size_t kLdsTreeBytes = 32768;
 
-// Ray slots per lane in the refill counting kernel (0 disables it); the
-// OGV_REFILL environment variable overrides it, for measurement.
-int refill_waves_default() {
-    const char *e = std::getenv("OGV_REFILL");
-    return e ? std::max(0, std::atoi(e)) : 4;
-}
-const int g_refill_waves = refill_waves_default();
 
 struct Bufs {
     int32_t *counts, *nruns;
@@ -306,8 +253,10 @@ Bufs bufs_of(void *ws, const Plan &p) {
     b.pool.ray_next = (int32_t *)(w + p.off_next);
     b.pool.chunks = (int2 *)(w + p.off_chunks);
     b.pool.chunk_next = (int32_t *)(w + p.off_cnext);
-    b.pool.head = (int32_t *)(w + p.off_ntab) + 1;
+    b.pool.head = (int32_t *)(w + p.off_ntab) + 1;   // [0] n_tab, [1] pool head, [2] lost rays
     b.pool.cap = p.pool_cap;
+    b.pool.lost = (int32_t *)(w + p.off_lost);
+    b.pool.n_lost = (int32_t *)(w + p.off_ntab) + 2;
     b.tiles = (int64_t *)(w + p.off_tiles);
     return b;
 }
@@ -322,14 +271,7 @@ void launch_count(const GridView &g, const float *o, const float *d, int64_t n, 
     unsigned blocks = (unsigned)((tiled_threads(n, width) + kBlock - 1) / kBlock);
     size_t shm = kLds ? lds_bytes(g) : 0;
     pool_reset_kernel<<<1, 64, 0, s>>>(b.pool.head);
-    if (g.L == 1 && !kSkip && g_refill_waves > 0) {
-        const int64_t slots = tiled_threads(n, width);
-        const int per_wave = 64 * g_refill_waves;
-        const int64_t waves = (slots + per_wave - 1) / per_wave;
-        const unsigned rblocks = (unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64));
-        count_refill_kernel<kVdb, kLds>
-            <<<rblocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool, width, slots, per_wave);
-    } else if (g.L == 1)
+    if (g.L == 1)
         count_kernel<kVdb, kSkip, kLds, true>
             <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool, width);
     else
@@ -337,18 +279,22 @@ void launch_count(const GridView &g, const float *o, const float *d, int64_t n, 
             <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool, width);
 }
 
+// Lost-ray fills run on a small grid that strides through the list.
+constexpr unsigned kListBlocks = 64;
+
 template <bool kVdb, bool kSkip, bool kLds>
 void launch_fill(const GridView &g, const float *o, const float *d, int64_t n, const Lattice &lat,
                  const int64_t *offsets, int64_t cap, int32_t *ids, float *t0, float *t1, int32_t *vox,
-                 const int32_t *only_overflow, hipStream_t s) {
+                 const int32_t *list, const int32_t *list_len, hipStream_t s) {
     unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
+    if (list) blocks = std::min(blocks, kListBlocks);
     size_t shm = kLds ? lds_bytes(g) : 0;
     if (vox)
         fill_kernel<kVdb, kSkip, true, kLds>
-            <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, offsets, cap, ids, t0, t1, vox, only_overflow);
+            <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, offsets, cap, ids, t0, t1, vox, list, list_len);
     else
         fill_kernel<kVdb, kSkip, false, kLds>
-            <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, offsets, cap, ids, t0, t1, vox, only_overflow);
+            <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, offsets, cap, ids, t0, t1, vox, list, list_len);
 }
 
 void dispatch_count(const GridView &g, int variant, const float *o, const float *d, int64_t n, const Lattice &lat,
@@ -368,9 +314,9 @@ void dispatch_count(const GridView &g, int variant, const float *o, const float 
 
 void dispatch_fill(const GridView &g, int variant, const float *o, const float *d, int64_t n, const Lattice &lat,
                    const int64_t *offsets, int64_t cap, int32_t *ids, float *t0, float *t1, int32_t *vox,
-                   const int32_t *only_overflow, hipStream_t s) {
+                   const int32_t *list, const int32_t *list_len, hipStream_t s) {
     const bool lds = lds_bytes(g) <= kLdsTreeBytes;
-#define OGV_FILL(V, K, L) launch_fill<V, K, L>(g, o, d, n, lat, offsets, cap, ids, t0, t1, vox, only_overflow, s)
+#define OGV_FILL(V, K, L) launch_fill<V, K, L>(g, o, d, n, lat, offsets, cap, ids, t0, t1, vox, list, list_len, s)
     if (g.kind == 0) {
         if (variant == OGV_SKIP) OGV_FILL(false, true, false);
         else OGV_FILL(false, false, false);
@@ -420,15 +366,15 @@ ogv_status fill_all(const ogv_grid *grid, int32_t variant, const float *o, const
     if (n == 0 || cap == 0) return OGV_OK;
     Bufs b = bufs_of(ws, p);
     if (vox) {
-        dispatch_fill(grid->view, variant, o, d, n, lat, offsets, cap, ids, t0, t1, vox, nullptr, s);
+        dispatch_fill(grid->view, variant, o, d, n, lat, offsets, cap, ids, t0, t1, vox, nullptr, nullptr, s);
         OGV_CHECK_LAUNCH();
         return OGV_OK;
     }
     unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
-    const int vec4 = (((uintptr_t)ids | (uintptr_t)t0 | (uintptr_t)t1) & 15) == 0;
-    expand_kernel<<<blocks, kBlock, 0, s>>>(offsets, n, b.nruns, reader_of(b), lat, cap, ids, t0, t1, vec4);
+    expand_kernel<<<blocks, kBlock, 0, s>>>(offsets, n, b.nruns, reader_of(b), lat, cap, ids, t0, t1);
     OGV_CHECK_LAUNCH();
-    dispatch_fill(grid->view, variant, o, d, n, lat, offsets, cap, ids, t0, t1, nullptr, b.nruns, s);
+    dispatch_fill(grid->view, variant, o, d, n, lat, offsets, cap, ids, t0, t1, nullptr, b.pool.lost, b.pool.n_lost,
+                  s);
     OGV_CHECK_LAUNCH();
     return OGV_OK;
 }
@@ -476,6 +422,42 @@ extern "C" ogv_status ogv_sample_count(const ogv_grid *grid, const ogv_sample_op
     if ((st = build_table(near_t, far_t, step, ws, p, s)) != OGV_OK) return st;
     Lattice lat = make_lattice(near_t, far_t, step, ws, p);
     return count_and_scan(grid, opts.variant, opts.image_width, o, d, n, lat, offsets, ws, p, 0, nullptr, s);
+}
+
+extern "C" ogv_status ogv_sample_count_raw(const ogv_grid *grid, const ogv_sample_opts *opts_p, const float *o,
+                                           const float *d, int64_t n, float near_t, float far_t,
+                                           const ogv_step *step, void *ws, size_t ws_bytes, void *stream) {
+    const ogv_sample_opts opts = opts_of(opts_p);
+    Plan p;
+    ogv_status st = prepare(grid, opts, o, d, n, near_t, far_t, step, ws, ws_bytes, &p, "ogv_sample_count_raw");
+    if (st != OGV_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = build_table(near_t, far_t, step, ws, p, s)) != OGV_OK) return st;
+    if (n == 0) return OGV_OK;
+    Lattice lat = make_lattice(near_t, far_t, step, ws, p);
+    dispatch_count(grid->view, opts.variant, o, d, n, lat, bufs_of(ws, p), opts.image_width, s);
+    OGV_CHECK_LAUNCH();
+    return OGV_OK;
+}
+
+extern "C" ogv_status ogv_sample_scan(int64_t n, int64_t *offsets, void *ws, size_t ws_bytes, void *stream) {
+    if (n < 0 || n > (int64_t)INT32_MAX) OGV_FAIL(OGV_ERR_INVALID, "n_rays out of range");
+    if (!offsets) OGV_FAIL(OGV_ERR_INVALID, "offsets is null");
+    // counts and scan tiles sit at offsets that depend on n_rays alone
+    const ogv_step unit{OGV_STEP_CONST, 1.0f, 0.0f, 0.0f};
+    Plan p;
+    std::string why;
+    if (!make_plan(n, 0.0f, 0.0f, &unit, &p, &why)) OGV_FAIL(OGV_ERR_UNSUPPORTED, why);
+    if (!ws || ws_bytes < p.off_tab) OGV_FAIL(OGV_ERR_CAPACITY, "workspace smaller than the count call's");
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {
+        zero_kernel<<<1, 64, 0, s>>>(offsets, nullptr);
+        OGV_CHECK_LAUNCH();
+        return OGV_OK;
+    }
+    Bufs b = bufs_of(ws, p);
+    OGV_CHECK_HIP(launch_excl_scan(b.counts, n, offsets, b.tiles, 0, nullptr, s));
+    return OGV_OK;
 }
 
 extern "C" ogv_status ogv_sample_fill(const ogv_grid *grid, const ogv_sample_opts *opts_p, const float *o,

@@ -119,106 +119,136 @@ __device__ __forceinline__ Tree load_tree(const GridView &g, uint64_t *smem) {
 
 // VDB tree: the current cell is the largest uniform cell holding the current
 // voxel -- a root tile (D = 8*S voxels per axis), an internal-node tile
-// (D = 8) or a leaf voxel (D = 1).  The cell's exit is the first crossing of
-// its far planes (for D = 1 that is the ordinary voxel step); leaving a tile
-// moves the stepping axis past it and re-locates the other axes exactly at
-// the exit parameter.
+// (D = 8) or a leaf voxel (D = 1).  Its exit is the first crossing of its far
+// planes (for D = 1 the ordinary voxel step).
+//
+// The walk is incremental, as in a plain DDA: a step moves the stepping axis
+// into the next cell and looks that cell up; when it has the same size as the
+// cell left, only the stepping axis's exit plane moves (D planes further).
+// The other axes stay inside their D-aligned blocks while tiles are crossed,
+// so their voxels are only re-located (exactly, at the exit parameter) when
+// the walk descends into a finer cell; a change of size recomputes all three
+// exits.  Cell sequence and exit parameters equal those of a walk that
+// re-locates every axis at every exit.
 struct VdbCursor {
     Tree t;
     int lev, R, sh;
     Axis A0, A1, A2;
-    int u0, u1, u2;        // ray-order voxel per moving axis
+    int u0, u1, u2;        // ray-order voxel per moving axis (inside the current cell's block)
     int v0, v1, v2;        // voxel index per axis
-    int k0, k1, k2;        // ray-order exit plane of the current cell per axis
+    int k0, k1, k2;        // ray-order exit plane of the current cell per moving axis
+    float e0, e1, e2;      // their crossing parameters (+inf for zero axes)
+    int kx;                // exit plane of the axis exit() chose
     int D;                 // current cell size in voxels
+    bool occ;              // current cell occupied
     int lblk;              // cached leaf block (packed block coordinates), -1 if none
     int lbase;             // its first word in the leaf array
-    int wx;                // cached word: voxel x within the leaf
+    int wx;                // cached word: voxel x within the leaf (-1: none)
     uint64_t word;
 
-    __device__ __forceinline__ bool occupied() {
-        // inside the cached leaf: no tree lookup, at most one word load
+    // Size of the largest uniform cell holding voxel (v0, v1, v2) and its
+    // occupancy; for a voxel inside a leaf the leaf and word are cached.
+    __device__ __forceinline__ int classify(bool &o) {
         const int blk = ((v0 >> 3) << 20) | ((v1 >> 3) << 10) | (v2 >> 3);
-        if (blk == lblk) {
-            if ((v0 & 7) != wx) {
-                wx = v0 & 7;
-                word = t.leaves[lbase + wx];
+        if (blk != lblk) {
+            const int NR = t.NR;
+            const int ri = ((lev * NR + (v0 >> sh)) * NR + (v1 >> sh)) * NR + (v2 >> sh);
+            const int node = t.root[ri];
+            if (node < 0) {
+                o = node == -2;
+                return 8 << t.ilog2;
             }
-            D = 1;
-            return (word >> (((v1 & 7) << 3) | (v2 & 7))) & 1ull;
+            const int m = t.S - 1;
+            const int s = (((v0 >> 3) & m) * t.S + ((v1 >> 3) & m)) * t.S + ((v2 >> 3) & m);
+            const int w = node * t.W + (s >> 6);
+            const uint64_t cm = t.child[w];
+            const uint64_t bit = 1ull << (s & 63);
+            if (!(cm & bit)) {
+                o = (t.value[w] & bit) != 0;
+                return 8;
+            }
+            lblk = blk;
+            lbase = (int)(t.rank[w] + (uint32_t)__popcll(cm & (bit - 1))) * 8;
+            wx = -1;
         }
-        const int NR = t.NR;
-        int ri = ((lev * NR + (v0 >> sh)) * NR + (v1 >> sh)) * NR + (v2 >> sh);
-        int node = t.root[ri];
-        if (node < 0) {
-            D = 8 << t.ilog2;
-            return node == -2;
+        if ((v0 & 7) != wx) {
+            wx = v0 & 7;
+            word = t.leaves[lbase + wx];
         }
-        const int m = t.S - 1;
-        int s = (((v0 >> 3) & m) * t.S + ((v1 >> 3) & m)) * t.S + ((v2 >> 3) & m);
-        int w = node * t.W + (s >> 6);
-        uint64_t cm = t.child[w];
-        uint64_t bit = 1ull << (s & 63);
-        if (!(cm & bit)) {
-            D = 8;
-            return (t.value[w] & bit) != 0;
-        }
-        lblk = blk;
-        lbase = (int)(t.rank[w] + (uint32_t)__popcll(cm & (bit - 1))) * 8;
-        wx = v0 & 7;
-        word = t.leaves[lbase + wx];
-        D = 1;
-        return (word >> (((v1 & 7) << 3) | (v2 & 7))) & 1ull;
+        o = (word >> (((v1 & 7) << 3) | (v2 & 7))) & 1ull;
+        return 1;
     }
 
-    __device__ __forceinline__ float exit(int &axis) {
+    // exit planes and parameters of every moving axis for cells of size D
+    __device__ __forceinline__ void exits_all() {
         const float inf = __builtin_huge_valf();
         const int msk = ~(D - 1);
-        float e0 = inf, e1 = inf, e2 = inf;
+        e0 = e1 = e2 = inf;
         if (!A0.zero) {
-            int b = v0 & msk;
+            const int b = v0 & msk;
             k0 = A0.pos ? b + D : R - b;
             e0 = A0.Tk(k0);
         }
         if (!A1.zero) {
-            int b = v1 & msk;
+            const int b = v1 & msk;
             k1 = A1.pos ? b + D : R - b;
             e1 = A1.Tk(k1);
         }
         if (!A2.zero) {
-            int b = v2 & msk;
+            const int b = v2 & msk;
             k2 = A2.pos ? b + D : R - b;
             e2 = A2.Tk(k2);
         }
+    }
+
+    // the cell holding the current voxels becomes current
+    __device__ __forceinline__ void enter() {
+        bool o;
+        D = classify(o);
+        occ = o;
+        exits_all();
+    }
+
+    __device__ __forceinline__ bool occupied() const { return occ; }
+
+    // first exit crossing; also keeps that axis's exit plane for step()
+    __device__ __forceinline__ float exit(int &axis) {
         float hi = e0;
+        int k = k0;
         axis = 0;
-        if (e1 < hi) { hi = e1; axis = 1; }
-        if (e2 < hi) { hi = e2; axis = 2; }
+        if (e1 < hi) { hi = e1; k = k1; axis = 1; }
+        if (e2 < hi) { hi = e2; k = k2; axis = 2; }
+        kx = k;
         return hi;
     }
 
+    // moves into the next cell across the exit found by exit(); false when
+    // that leaves the grid
     __device__ __forceinline__ bool step(int axis, float t) {
-        if (axis == 0) {
-            if (k0 >= R) return false;
-            u0 = k0;
-        } else if (D > 1 && !A0.zero) {
-            u0 = A0.advance_to(u0, t, min(k0, R) - 1);
+        const int ka = kx;
+        if (ka >= R) return false;
+        if (axis == 0) { u0 = ka; v0 = A0.voxel(ka); }
+        if (axis == 1) { u1 = ka; v1 = A1.voxel(ka); }
+        if (axis == 2) { u2 = ka; v2 = A2.voxel(ka); }
+        bool o;
+        int Dn = classify(o);
+        if (Dn == D) {
+            // same cell size: the next exit along the stepping axis is D planes on
+            if (axis == 0) { k0 += D; e0 = A0.Tk(k0); }
+            if (axis == 1) { k1 += D; e1 = A1.Tk(k1); }
+            if (axis == 2) { k2 += D; e2 = A2.Tk(k2); }
+        } else {
+            if (Dn < D) {
+                // descending out of a tile: voxels of the other axes at t, inside their blocks
+                if (axis != 0 && !A0.zero) { u0 = A0.advance_to(u0, t, min(k0, R) - 1); v0 = A0.voxel(u0); }
+                if (axis != 1 && !A1.zero) { u1 = A1.advance_to(u1, t, min(k1, R) - 1); v1 = A1.voxel(u1); }
+                if (axis != 2 && !A2.zero) { u2 = A2.advance_to(u2, t, min(k2, R) - 1); v2 = A2.voxel(u2); }
+                Dn = classify(o);
+            }
+            D = Dn;
+            exits_all();
         }
-        if (axis == 1) {
-            if (k1 >= R) return false;
-            u1 = k1;
-        } else if (D > 1 && !A1.zero) {
-            u1 = A1.advance_to(u1, t, min(k1, R) - 1);
-        }
-        if (axis == 2) {
-            if (k2 >= R) return false;
-            u2 = k2;
-        } else if (D > 1 && !A2.zero) {
-            u2 = A2.advance_to(u2, t, min(k2, R) - 1);
-        }
-        if (!A0.zero) v0 = A0.voxel(u0);
-        if (!A1.zero) v1 = A1.voxel(u1);
-        if (!A2.zero) v2 = A2.voxel(u2);
+        occ = o;
         return true;
     }
 };
@@ -286,7 +316,7 @@ __device__ __forceinline__ void drive(Cursor &c, float a, float b, float tmax, V
 // the expansion fill.  A ray keeps its first kMaxRuns runs in fixed slots;
 // further runs go to chunks of kMaxRuns slots taken from a shared pool and
 // chained (ray_next -> pool_next -> ...).  If the pool runs dry the ray is
-// marked kRunsLost and the traversal fill writes it instead.
+// marked kRunsLost, listed, and the traversal fill writes it instead.
 constexpr int kMaxRuns = 16;
 constexpr int32_t kRunsLost = 0x7fffffff;
 
@@ -297,6 +327,8 @@ struct RunPool {
     int32_t *chunk_next;  // [cap]
     int32_t *head;        // chunks handed out so far
     int32_t cap;
+    int32_t *lost;        // [rays]: rays marked kRunsLost, in no particular order
+    int32_t *n_lost;      // their number
 };
 
 // Uniform context of the count pass.
@@ -350,6 +382,7 @@ struct CountVis {
     }
     __device__ __forceinline__ void finish(const CountCtx &x) {
         if (cur1 > cur0) store(x.pool, cur0, cur1);
+        if (nr == kRunsLost) x.pool.lost[atomicAdd(x.pool.n_lost, 1)] = (int32_t)ray;
     }
 };
 
@@ -466,11 +499,11 @@ __device__ __forceinline__ bool cursor_begin(typename CursorOf<kVdb>::type &c, c
         c.lev = lev;
         c.sh = 3 + tree.ilog2;
         c.k0 = c.k1 = c.k2 = 0;
-        c.D = 1;
         c.lblk = -1;
         c.lbase = 0;
-        c.wx = 0;
+        c.wx = -1;
         c.word = 0;
+        c.enter();
     }
     return true;
 }
@@ -553,70 +586,18 @@ __device__ __forceinline__ void trace_ray(const GridView &g, const Tree &tree, c
     }
 }
 
-// ------------------------------------------------------------------ resumable walk
-
-// A single-level ray walk in Alg. 1 form that advances one cell per call, so
-// a lane can drop a finished ray and take the next one (lane refill) instead
-// of idling until the slowest ray of its wave ends.
-template <bool kVdb>
-struct Walk {
-    typename CursorOf<kVdb>::type c;
-    float lo, b, run_lo;
-    bool in_run;
-};
-
-// false when the ray has nothing to walk
-template <bool kVdb, class Vis>
-__device__ __forceinline__ bool walk_begin(Walk<kVdb> &w, const GridView &g, const Tree &tree, const float o[3],
-                                           const float d[3], const Lattice &lat, Vis &vis) {
-    if (!(lat.tmin <= lat.tmax)) return false;
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-        if (!__builtin_isfinite(o[a]) || !__builtin_isfinite(d[a])) return false;
-    Ray ray{o[0], o[1], o[2], d[0], d[1], d[2], __fdiv_rn(1.0f, d[0]), __fdiv_rn(1.0f, d[1]), __fdiv_rn(1.0f, d[2])};
-    float E, X;
-    if (!span_of(g, 0, ray, E, X) || !(E < lat.tmax) || !(X >= lat.tmin) || !(E < X)) return false;
-    if (!cursor_begin<kVdb>(w.c, g, tree, 0, ray, E, lat, vis)) return false;
-    w.lo = E;
-    w.b = X;
-    w.in_run = false;
-    w.run_lo = E;
-    return true;
-}
-
-// one cell; true when the ray is finished
-template <bool kVdb, class Vis, class Ctx>
-__device__ __forceinline__ bool walk_step(Walk<kVdb> &w, float tmax, Vis &vis, const Ctx &ctx) {
-    const bool occ = w.c.occupied();
-    int axis;
-    const float hi = w.c.exit(axis);
-    if (occ && !w.in_run) {
-        w.in_run = true;
-        w.run_lo = w.lo;
-    }
-    bool end = hi >= w.b || hi >= tmax;
-    if (!end) end = !w.c.step(axis, hi);
-    if (w.in_run && (!occ || end)) {
-        vis.run(ctx, w.run_lo, occ ? fminf(hi, w.b) : w.lo);
-        w.in_run = false;
-    }
-    w.lo = hi;
-    return end;
-}
-
 // ------------------------------------------------------------------ expansion fill
 
-// Expansion fill: a block takes 256 consecutive rays, gathers their kept
-// runs into LDS with each run's first output index, and writes the block's
-// samples with consecutive lanes on consecutive outputs (coalesced): sample
-// j belongs to the last run starting at or before j.  Runs of rays flagged
-// by the count pass are absent; those samples are left to the traversal fill.
-constexpr int kExpandRuns = 1024;
-
+// Expansion fill: one wave per 64 consecutive rays.  Each lane loads its
+// ray's output offset, run count and first two runs in one round trip; the
+// wave then walks its rays in order (their values read out of the lanes as
+// wave-uniform scalars) and writes every run's samples with consecutive lanes
+// on consecutive outputs, so stores are contiguous and no lane searches for
+// its run.  Rays whose runs were lost are left to the traversal fill.
 struct OneLattice {       // every ray on one lattice
     Lattice lat;
     __device__ __forceinline__ int scene_of(int64_t) const { return 0; }
-    __device__ __forceinline__ float t(int, int n) const { return lat.t(n); }
+    __device__ __forceinline__ Lattice get(int) const { return lat; }
 };
 
 struct SceneLattices {    // ray r on the lattice of its scene
@@ -628,31 +609,9 @@ struct SceneLattices {    // ray r on the lattice of its scene
         while (s + 1 < n && first[s + 1] <= r) ++s;
         return s;
     }
-    __device__ __forceinline__ float t(int s, int k) const { return lats[s].t(k); }
+    __device__ __forceinline__ Lattice get(int s) const { return lats[s]; }
 };
 
-__device__ __forceinline__ int64_t block_excl_scan256(int64_t x, int64_t *lds, int64_t &total) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        int64_t y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) lds[wid] = x;
-    __syncthreads();
-    int64_t base = 0;
-    total = 0;
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
-        int64_t v = lds[w];
-        if (w < wid) base += v;
-        total += v;
-    }
-    __syncthreads();
-    return base + x;   // inclusive
-}
-
-// The run of ray r with index k (k < nruns[r]), following the pool chain.
 struct RunReader {
     const int2 *slots;
     const int32_t *ray_next;
@@ -660,90 +619,76 @@ struct RunReader {
     const int32_t *chunk_next;
 };
 
+__device__ __forceinline__ int64_t lane_value(int64_t x, int i) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, i);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)x >> 32), i);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 template <class Lats>
-__device__ __forceinline__ void expand_block(const int64_t *__restrict__ offsets, int64_t n_rays,
-                                             const int32_t *__restrict__ nruns, const RunReader &rd,
-                                             const Lats &lats, int64_t capacity, int32_t *__restrict__ ray_ids,
-                                             float *__restrict__ t0, float *__restrict__ t1, bool vec4) {
-    __shared__ int64_t s_start[kExpandRuns];
-    __shared__ int32_t s_n0[kExpandRuns], s_len[kExpandRuns], s_ray[kExpandRuns];
-    __shared__ int16_t s_scene[kExpandRuns];
-    __shared__ int64_t s_wave[kBlock / 64];
-    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    int nr = 0, scene = 0;
+__device__ __forceinline__ void expand_wave(const int64_t *__restrict__ offsets, int64_t n_rays,
+                                            const int32_t *__restrict__ nruns, const RunReader &rd,
+                                            const Lats &lats, int64_t capacity, int32_t *__restrict__ ray_ids,
+                                            float *__restrict__ t0, float *__restrict__ t1) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x - lane);   // the wave's first ray
+    if (r0 >= n_rays) return;                                                   // wave-uniform
+    const int64_t r = r0 + lane;
     int64_t off = 0;
+    int nr = 0, sc = 0;
+    int2 ra = make_int2(0, 0), rb = make_int2(0, 0);
     if (r < n_rays) {
-        nr = nruns[r];
-        if (nr == kRunsLost) nr = 0;
         off = offsets[r];
-        scene = lats.scene_of(r);
+        nr = nruns[r];
+        sc = lats.scene_of(r);
+        if (nr != kRunsLost && nr > 0) ra = rd.slots[r * kMaxRuns];
+        if (nr != kRunsLost && nr > 1) rb = rd.slots[r * kMaxRuns + 1];
     }
-    int64_t total;
-    const int rb = (int)(block_excl_scan256((int64_t)nr, s_wave, total) - nr);
-    for (int c0 = 0; c0 < (int)total; c0 += kExpandRuns) {
-        const int cn = min((int)total - c0, kExpandRuns);
-        int64_t start = off;
+    const int m = (int)min((int64_t)64, n_rays - r0);
+    for (int i = 0; i < m; ++i) {
+        const int nri = __builtin_amdgcn_readlane(nr, i);
+        if (nri == kRunsLost || nri == 0) continue;
+        int64_t pos = lane_value(off, i);
+        if (pos >= capacity) break;   // offsets never decrease: no later ray fits either
+        const int si = __builtin_amdgcn_readlane(sc, i);
+        const int64_t ray = r0 + i;
         int32_t chunk = -1;
-        for (int k = 0; k < nr; ++k) {
-            int2 rn;
-            if (k < kMaxRuns) {
-                rn = rd.slots[r * kMaxRuns + k];
+        for (int k = 0; k < nri; ++k) {
+            int2 run;
+            if (k == 0) {
+                run = make_int2(__builtin_amdgcn_readlane(ra.x, i), __builtin_amdgcn_readlane(ra.y, i));
+            } else if (k == 1) {
+                run = make_int2(__builtin_amdgcn_readlane(rb.x, i), __builtin_amdgcn_readlane(rb.y, i));
+            } else if (k < kMaxRuns) {
+                run = rd.slots[ray * kMaxRuns + k];
             } else {
-                if (k % kMaxRuns == 0) chunk = k == kMaxRuns ? rd.ray_next[r] : rd.chunk_next[chunk];
-                rn = rd.chunks[(int64_t)chunk * kMaxRuns + k % kMaxRuns];
+                if (k % kMaxRuns == 0) chunk = k == kMaxRuns ? rd.ray_next[ray] : rd.chunk_next[chunk];
+                run = rd.chunks[(int64_t)chunk * kMaxRuns + k % kMaxRuns];
             }
-            int idx = rb + k - c0;
-            if (idx >= 0 && idx < cn) {
-                s_start[idx] = start;
-                s_n0[idx] = rn.x;
-                s_len[idx] = rn.y - rn.x;
-                s_ray[idx] = (int32_t)r;
-                s_scene[idx] = (int16_t)scene;
-            }
-            start += rn.y - rn.x;
-        }
-        __syncthreads();
-        const int64_t lo = s_start[0];
-        const int64_t hi = min(s_start[cn - 1] + (int64_t)s_len[cn - 1], capacity);
-        // each lane takes 4 consecutive samples: one search, 16-byte stores
-        for (int64_t j4 = (lo & ~(int64_t)3) + 4 * (int64_t)threadIdx.x; j4 < hi; j4 += 4 * kBlock) {
-            const int64_t jf = j4 < lo ? lo : j4;
-            int a = 0, b = cn - 1;   // last run with start <= jf
-            while (a < b) {
-                int mid = (a + b + 1) >> 1;
-                if (s_start[mid] <= jf) a = mid;
-                else b = mid - 1;
-            }
-            int32_t id[4];
-            float x0[4], x1[4];
-            bool ok[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t j = j4 + q;
-                while (a + 1 < cn && s_start[a + 1] <= j) ++a;
-                const int64_t rel = j - s_start[a];
-                ok[q] = j >= lo && j < hi && rel >= 0 && rel < s_len[a];
-                const int sc = s_scene[a];
-                const int n = s_n0[a] + (int)rel;
-                id[q] = s_ray[a];
-                x0[q] = ok[q] ? lats.t(sc, n) : 0.0f;
-                x1[q] = ok[q] ? lats.t(sc, n + 1) : 0.0f;
-            }
-            if (vec4 && ok[0] && ok[1] && ok[2] && ok[3]) {
-                *reinterpret_cast<int4 *>(ray_ids + j4) = make_int4(id[0], id[1], id[2], id[3]);
-                *reinterpret_cast<float4 *>(t0 + j4) = make_float4(x0[0], x0[1], x0[2], x0[3]);
-                *reinterpret_cast<float4 *>(t1 + j4) = make_float4(x1[0], x1[1], x1[2], x1[3]);
+            const int len = run.y - run.x;
+            // uniform bases, 32-bit lane offsets; the constant-step loop holds no
+            // load, so its stores are never made to wait for one another
+            const int lim = (int)min((int64_t)len, capacity - pos);
+            int32_t *__restrict__ oid = ray_ids + pos;
+            float *__restrict__ o0 = t0 + pos;
+            float *__restrict__ o1 = t1 + pos;
+            const Lattice L = lats.get(si);
+            if (!L.cone) {
+                for (int c = lane; c < lim; c += 64) {
+                    oid[c] = (int32_t)ray;
+                    o0[c] = L.t(run.x + c);
+                    o1[c] = L.t(run.x + c + 1);
+                }
             } else {
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (ok[q]) {
-                        ray_ids[j4 + q] = id[q];
-                        t0[j4 + q] = x0[q];
-                        t1[j4 + q] = x1[q];
-                    }
+                for (int c = lane; c < lim; c += 64) {
+                    const float a = L.tab[run.x + c], b = L.tab[run.x + c + 1];
+                    oid[c] = (int32_t)ray;
+                    o0[c] = a;
+                    o1[c] = b;
+                }
             }
+            pos += len;
         }
-        __syncthreads();
     }
 }
 

@@ -285,3 +285,34 @@ def test_determinism(obj):
     b = gpu_sample(g, obj.origins, obj.dirs, obj.near, obj.far, obj.step, "skip", voxel_ids=False)
     for k in a:
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_split_count_matches_count_and_fills_the_same(obj):
+    # ogv_sample_count == ogv_sample_count_raw + ogv_sample_scan, and the fill
+    # after the split writes the same samples as the one-call path
+    o = torch.from_numpy(obj.origins).cuda()
+    d = torch.from_numpy(obj.dirs).cuda()
+    for kind in ("vdb", "dense"):
+        g = gpu_grid(kind, obj.occ, obj.boxes, obj.ilog2)
+        sp = api.Sampler(g, obj.n_rays, obj.near, obj.far, api.make_step(obj.step), "branch",
+                         image_width=obj.image[0])
+        whole = sp.count(o, d).clone()
+        sp.offsets.fill_(-7)
+        sp.count_raw(o, d)
+        split = sp.scan().clone()
+        torch.cuda.synchronize()
+        assert torch.equal(whole, split), kind
+        S = int(split[-1].item())
+        ids = torch.empty(S, dtype=torch.int32, device="cuda")
+        t0 = torch.empty(S, device="cuda")
+        t1 = torch.empty(S, device="cuda")
+        sp.fill(o, d, ids, t0, t1)
+        ref = gpu_sample(g, obj.origins, obj.dirs, obj.near, obj.far, obj.step, "branch", voxel_ids=False,
+                         image_width=obj.image[0])
+        torch.cuda.synchronize()
+        assert_same({"offsets": split.cpu().numpy(), "ray_ids": ids.cpu().numpy(), "t0": t0.cpu().numpy(),
+                     "t1": t1.cpu().numpy()}, ref, kind)
+    empty = api.Sampler(g, 0, obj.near, obj.far, api.make_step(obj.step))
+    e = torch.zeros((0, 3), device="cuda")
+    empty.count_raw(e, e)
+    assert empty.scan().cpu().tolist() == [0]

@@ -53,3 +53,20 @@ def test_host_side_validation_without_gpu():
     nested_wrong = (ctypes.c_float * 12)(-2, -2, -2, 2, 2, 2, -1, -1, -1, 1, 1, 1)
     assert L.ogv_dense_build(2, 8, nested_wrong, ctypes.c_void_p(1), ctypes.byref(h), None) == -1
     assert b"contain" in L.ogv_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_scan_entry_validates_on_host():
+    # ogv_sample_scan locates the counts from n_rays alone; it refuses a
+    # workspace smaller than the count call's prefix, null offsets and bad n
+    from paper_2404_10272_amd import api
+    L = api.lib()
+    n = ctypes.c_size_t()
+    unit = api.make_step("const", dt=5e-3)
+    assert L.ogv_sample_workspace_size(1000, 2.0, 6.0, ctypes.byref(unit), ctypes.byref(n)) == 0
+    fake = ctypes.c_void_p(1 << 20)   # never dereferenced: every call below fails its host checks
+    assert L.ogv_sample_scan(-1, fake, fake, n.value, None) == -1
+    assert L.ogv_sample_scan(1000, None, fake, n.value, None) == -1
+    assert L.ogv_sample_scan(1000, fake, None, n.value, None) == -2
+    assert L.ogv_sample_scan(1000, fake, fake, 64, None) == -2
+    assert b"workspace" in L.ogv_last_error()
