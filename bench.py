@@ -34,8 +34,10 @@ def parse():
     p.add_argument("--variant", default="branch", choices=["skip", "branch"],
                    help="loop structure of the timed VDB sampler (Alg. 1 branch / Alg. 2 skip)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    p.add_argument("--cpu-stride", type=int, default=4, help="oracle baseline uses every k-th ray")
+    p.add_argument("--cpu-stride", type=int, default=1, help="oracle baseline uses every k-th ray")
     p.add_argument("--no-side", action="store_true", help="skip the composite and batched side measurements")
+    p.add_argument("--primary-only", action="store_true",
+                   help="time only the headline VDB step (no variant or dense comparisons; for profiling)")
     p.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                    help="first run a plain device copy of MIB MiB (3 times), to calibrate HBM byte counters")
     return p.parse_args()
@@ -176,21 +178,30 @@ def batched_side(api, torch, scenes, steps):
             "tune": {"chunk": info["chunk"], "blocks_per_cu": info["blocks_per_cu"], "tuned": info["tuned"]}}
 
 
-def cpu_baseline(w, stride):
+def cpu_baseline(w, stride, min_s=10.0, max_s=30.0):
+    """The oracle (VDB + hierarchical DDA, Alg. 2 loop, count + fill) on the
+    host cores, over every `stride`-th ray of the workload, repeated until at
+    least min_s seconds have passed (stopping before max_s)."""
     import numpy as np
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
     scene = oracle.Scene(w.occ, w.boxes)
     sub = slice(0, None, stride)
-    o, d = w.origins[sub], w.dirs[sub]
+    o, d = np.ascontiguousarray(w.origins[sub]), np.ascontiguousarray(w.dirs[sub])
     scene.vdb(w.ilog2)  # build outside the timed region, as on the GPU
-    t = time.perf_counter()
-    out = oracle.sample_rays(scene, o, d, w.near, w.far, w.step, "hdda_skip", ilog2=w.ilog2, threads=threads)
-    dt = time.perf_counter() - t
-    n = o.shape[0]
-    return {"value": n / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
-            "sample": f"every {stride}th ray of the workload ({n} rays, {int(out['offsets'][-1])} samples), "
-                      f"VDB + hierarchical DDA (Alg. 2 loop), count + fill, {dt:.2f} s wall"}
+    n, reps, spent, samples = o.shape[0], 0, 0.0, 0
+    while spent < min_s:
+        t = time.perf_counter()
+        out = oracle.sample_rays(scene, o, d, w.near, w.far, w.step, "hdda_skip", ilog2=w.ilog2, threads=threads)
+        one = time.perf_counter() - t
+        spent += one
+        reps += 1
+        samples = int(out["offsets"][-1])
+        if spent + one > max_s:
+            break
+    return {"value": reps * n / spent, "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {stride}th ray of the workload ({n} rays, {samples} samples) x {reps} repeats, "
+                      f"VDB + hierarchical DDA (Alg. 2 loop), count + fill, {spent:.1f} s wall"}
 
 
 def main():
@@ -229,18 +240,30 @@ def main():
     other = "skip" if args.variant == "branch" else "branch"
     W = w.image[0]
     hdda = Timed(api, torch, vdb, w, o, d, args.variant, W)
-    hdda_other = Timed(api, torch, vdb, w, o, d, other, W)
-    hdda_rows = Timed(api, torch, vdb, w, o, d, args.variant, 0)
-    plain = Timed(api, torch, dense, w, o, d, "branch", W)
-    plain_skip = Timed(api, torch, dense, w, o, d, "skip", W)
-    plain_rows = Timed(api, torch, dense, w, o, d, "branch", 0)
-    assert hdda.S == plain.S == hdda_other.S == plain_skip.S, "samplers disagree on the sample count"
     ms, walk_ms, scan_ms, fill_ms = hdda.run(args.steps, args.warmup)
-    oms, owalk_ms, oscan_ms, ofill_ms = hdda_other.run(args.steps, args.warmup)
-    rms = hdda_rows.run(args.steps, args.warmup)[0]
-    dms, dwalk_ms, dscan_ms, dfill_ms = plain.run(args.steps, args.warmup)
-    dsms, dswalk_ms, dsscan_ms, dsfill_ms = plain_skip.run(args.steps, args.warmup)
-    drms = plain_rows.run(args.steps, args.warmup)[0]
+    compare = {}
+    if not args.primary_only:
+        # the other loop variant, row-major lanes, and the dense-grid march
+        hdda_other = Timed(api, torch, vdb, w, o, d, other, W)
+        hdda_rows = Timed(api, torch, vdb, w, o, d, args.variant, 0)
+        plain = Timed(api, torch, dense, w, o, d, "branch", W)
+        plain_skip = Timed(api, torch, dense, w, o, d, "skip", W)
+        plain_rows = Timed(api, torch, dense, w, o, d, "branch", 0)
+        assert hdda.S == plain.S == hdda_other.S == plain_skip.S, "samplers disagree on the sample count"
+        N_ = w.n_rays
+
+        def rec(t):
+            tms, tw, ts, tf = t.run(args.steps, args.warmup)
+            return {"ms_per_step": tms, "count_scan_ms": tw + ts, "walk_ms": tw, "fill_ms": tf,
+                    "rays_per_s": N_ / (tms * 1e-3)}
+
+        compare["vdb_" + other] = rec(hdda_other)
+        compare["vdb_row_major_lanes"] = rec(hdda_rows)
+        compare["dense"] = dict(rec(plain), bytes=dinfo["bytes"], variant="branch")
+        compare["dense"]["samples_per_s"] = plain.S / (compare["dense"]["ms_per_step"] * 1e-3)
+        compare["dense_skip"] = rec(plain_skip)
+        compare["dense_row_major_lanes"] = rec(plain_rows)
+        compare["speedup_vs_dense"] = compare["dense"]["ms_per_step"] / ms
     count_ms = walk_ms + scan_ms
     N, S = w.n_rays, hdda.S
     G = vinfo["bytes"]
@@ -291,19 +314,6 @@ def main():
         "vdb": {"ms_per_step": ms, "count_scan_ms": count_ms, "walk_ms": walk_ms, "scan_ms": scan_ms,
                 "fill_ms": fill_ms, "rays_per_s": N / (ms * 1e-3),
                 "bytes": G, "leaves": vinfo["n_leaves"], "build_ms": build_ms},
-        "vdb_" + other: {"ms_per_step": oms, "count_scan_ms": owalk_ms + oscan_ms, "walk_ms": owalk_ms,
-                         "fill_ms": ofill_ms,
-                         "rays_per_s": N / (oms * 1e-3)},
-        "vdb_row_major_lanes": {"ms_per_step": rms, "rays_per_s": N / (rms * 1e-3)},
-        "dense_row_major_lanes": {"ms_per_step": drms, "rays_per_s": N / (drms * 1e-3)},
-        "dense": {"ms_per_step": dms, "count_scan_ms": dwalk_ms + dscan_ms, "walk_ms": dwalk_ms,
-                  "fill_ms": dfill_ms,
-                  "rays_per_s": N / (dms * 1e-3), "samples_per_s": S / (dms * 1e-3), "bytes": dinfo["bytes"],
-                  "variant": "branch"},
-        "dense_skip": {"ms_per_step": dsms, "count_scan_ms": dswalk_ms + dsscan_ms, "walk_ms": dswalk_ms,
-                       "fill_ms": dsfill_ms,
-                       "rays_per_s": N / (dsms * 1e-3)},
-        "speedup_vs_dense": dms / ms,
         "step_bytes": step_bytes,
         "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "runs": runs,
@@ -313,6 +323,7 @@ def main():
                      "stages_ms": {"walk": walk_ms, "scan": scan_ms, "fill": fill_ms},
                      "stage_bytes": {"walk": walk_bytes, "scan": 4 * N + 8 * (N + 1), "fill": fill_bytes}},
     }
+    line.update(compare)
     if not args.no_side:
         line["composite"] = composite_side(api, torch, scenes, hdda, N, min(args.steps, 20))
         line["batched"] = batched_side(api, torch, scenes, min(args.steps, 10))

@@ -104,8 +104,9 @@ __global__ void __launch_bounds__(kBlock) batch_expand_kernel(const int64_t *__r
                                                               const Lattice *__restrict__ lats,
                                                               const int64_t *__restrict__ first, int n_scenes,
                                                               int64_t capacity, int32_t *__restrict__ ray_ids,
-                                                              float *__restrict__ t0, float *__restrict__ t1) {
-    expand_wave(offsets, n_total, nruns, rd, SceneLattices{lats, first, n_scenes}, capacity, ray_ids, t0, t1);
+                                                              float *__restrict__ t0, float *__restrict__ t1, int vec4) {
+    expand_block(offsets, n_total, nruns, rd, SceneLattices{lats, first, n_scenes}, capacity, ray_ids, t0, t1,
+                 vec4 != 0);
 }
 
 template <bool kSkip>
@@ -215,8 +216,9 @@ hipError_t enqueue_pass(ogv_batch *b, int64_t *offsets, int64_t capacity, int32_
     if (e != hipSuccess || capacity == 0) return e;
     unsigned blocks = (unsigned)((b->n_total + kBlock - 1) / kBlock);
     const RunReader rd{b->pool.slots, b->pool.ray_next, b->pool.chunks, b->pool.chunk_next};
+    const int vec4 = (((uintptr_t)ids | (uintptr_t)t0 | (uintptr_t)t1) & 15) == 0;
     batch_expand_kernel<<<blocks, kBlock, 0, s>>>(offsets, b->n_total, b->nruns, rd, b->lats_dev, b->first_dev,
-                                                  b->n_scenes, capacity, ids, t0, t1);
+                                                  b->n_scenes, capacity, ids, t0, t1, vec4);
     // rays whose runs were lost (rare): a small grid strides through their list
     const unsigned lblocks = std::min(blocks, 64u);
     if (b->variant == OGV_SKIP)

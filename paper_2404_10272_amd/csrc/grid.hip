@@ -11,8 +11,8 @@
 //      full root tile, else an internal node;
 //   3. exclusive scans number the nodes and the leaves (mixed blocks under
 //      node roots, in root-then-slot order);
-//   4. write the root table, node masks (child, value, per-word leaf rank)
-//      and leaf masks.
+//   4. write the root table, node masks (child, value, per-word leaf rank),
+//      the nodes' per-slot child tables and leaf masks.
 #pragma clang fp contract(off)
 
 #include <hip/hip_runtime.h>
@@ -193,7 +193,8 @@ __global__ void __launch_bounds__(256) node_write_kernel(BuildDims b, const int3
                                                         const int32_t *__restrict__ kind,
                                                         const int64_t *__restrict__ leaf_idx,
                                                         uint64_t *__restrict__ child, uint64_t *__restrict__ value,
-                                                        uint32_t *__restrict__ rank, VdbCounts *counts) {
+                                                        uint32_t *__restrict__ rank, int32_t *__restrict__ slot,
+                                                        VdbCounts *counts) {
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int64_t job = (int64_t)blockIdx.x * 4 + wid;
     if (job >= b.n_root * b.W) return;
@@ -203,6 +204,8 @@ __global__ void __launch_bounds__(256) node_write_kernel(BuildDims b, const int3
     int64_t node = node_idx[r];
     int64_t s = (int64_t)w * 64 + lane;
     int k = s < b.n_slot ? kind[r * b.n_slot + s] : -1;
+    if (s < b.n_slot)
+        slot[node * b.n_slot + s] = k == 2 ? (int32_t)leaf_idx[r * b.n_slot + s] : (k == 1 ? -2 : -1);
     uint64_t cm = __ballot(k == 2);
     uint64_t vm = __ballot(k == 1);
     uint64_t em = __ballot(k == 0);
@@ -370,6 +373,7 @@ extern "C" ogv_status ogv_vdb_build(int32_t L, int32_t R, const float *boxes, co
     size_t o_child = take(sizeof(uint64_t) * b.n_root * b.W);
     size_t o_value = take(sizeof(uint64_t) * b.n_root * b.W);
     size_t o_rank = take(sizeof(uint32_t) * b.n_root * b.W);
+    size_t o_slot = take(sizeof(int32_t) * b.n_root * b.n_slot);
     size_t o_leaves = take(sizeof(uint64_t) * 8 * b.n_block);
     size_t total = off;
     // build scratch
@@ -414,6 +418,7 @@ extern "C" ogv_status ogv_vdb_build(int32_t L, int32_t R, const float *boxes, co
     v.child = (const uint64_t *)(m + o_child);
     v.value = (const uint64_t *)(m + o_value);
     v.rank = (const uint32_t *)(m + o_rank);
+    v.slot = (const int32_t *)(m + o_slot);
     v.leaves = (const uint64_t *)(m + o_leaves);
     g->counts_dev = (VdbCounts *)(m + o_counts);
 
@@ -441,7 +446,7 @@ extern "C" ogv_status ogv_vdb_build(int32_t L, int32_t R, const float *boxes, co
     if (e == hipSuccess) {
         node_write_kernel<<<(unsigned)((b.n_root * b.W + 3) / 4), 256, 0, s>>>(
             b, root_kind, node_idx, kind, leaf_idx, (uint64_t *)v.child, (uint64_t *)v.value, (uint32_t *)v.rank,
-            g->counts_dev);
+            (int32_t *)v.slot, g->counts_dev);
         leaf_write_kernel<<<(unsigned)((b.n_block * 8 + 255) / 256), 256, 0, s>>>(b, mixed, leaf_idx, masks,
                                                                                  (uint64_t *)v.leaves, g->counts_dev);
         e = hipGetLastError();
@@ -478,7 +483,7 @@ extern "C" ogv_status ogv_grid_info_get(const ogv_grid *grid, ogv_grid_info *inf
         g->counts_ready = true;
         const int64_t n_root = (int64_t)v.L * v.NR * v.NR * v.NR;
         g->used_bytes = (size_t)(n_root * 4 + g->counts_host.n_nodes * (int64_t)v.W * (8 + 8 + 4) +
-                                 g->counts_host.n_leaves * 64);
+                                 g->counts_host.n_nodes * (int64_t)v.S * v.S * v.S * 4 + g->counts_host.n_leaves * 64);
     }
     const VdbCounts &c = g->counts_host;
     info->bytes = (int64_t)g->used_bytes;

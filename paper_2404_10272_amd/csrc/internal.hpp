@@ -40,6 +40,9 @@ constexpr int kMaxLevels = OGV_MAX_LEVELS;
 //   child  uint64 [nodes][W]  bit s: slot s holds a leaf
 //   value  uint64 [nodes][W]  bit s: slot s is a full tile (when not a leaf)
 //   rank   uint32 [nodes][W]  leaf index of the first leaf in word w
+//   slot   int32  [nodes][S^3] per slot: leaf index (>= 0), -1 empty tile,
+//                              -2 full tile (the node's child table, which
+//                              the walk reads; the masks serve decoding)
 //   leaves uint64 [leaves][8] word x (voxel x&7), bit (y&7)*8 + (z&7)
 // with S = 2^ilog2 slots per axis per node, slot s = (sx*S + sy)*S + sz,
 // W = ceil(S^3 / 64) words per mask.  A root cell covers D = 8*S voxels.
@@ -54,6 +57,7 @@ struct GridView {
     const uint64_t *child;
     const uint64_t *value;
     const uint32_t *rank;
+    const int32_t *slot;
     const uint64_t *leaves;
 };
 

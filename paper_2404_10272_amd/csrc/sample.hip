@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(kBlock) count_kernel(GridView g, const float *
                                                        const float *__restrict__ dirs, int64_t n_rays, Lattice lat,
                                                        int32_t *__restrict__ counts, int32_t *__restrict__ nruns,
                                                        RunPool pool, int image_width) {
-    extern __shared__ uint64_t smem[];
+    extern __shared__ uint32_t smem[];
     Tree tree = kVdb ? load_tree<kLds>(g, smem) : Tree{};
     const int64_t i = ray_of_thread((int64_t)blockIdx.x * kBlock + threadIdx.x, n_rays, image_width);
     if (i < 0) return;
@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(kBlock) fill_kernel(GridView g, const float *_
                                                       float *__restrict__ t1, int32_t *__restrict__ vox,
                                                       const int32_t *__restrict__ list,
                                                       const int32_t *__restrict__ list_len) {
-    extern __shared__ uint64_t smem[];
+    extern __shared__ uint32_t smem[];
     const int64_t m = list ? (int64_t)*list_len : n_rays;
     if ((int64_t)blockIdx.x * kBlock >= m) return;   // block-uniform: no work, skip the staging too
     Tree tree = kVdb ? load_tree<kLds>(g, smem) : Tree{};
@@ -88,8 +88,9 @@ __global__ void pool_reset_kernel(int32_t *head) {
 __global__ void __launch_bounds__(kBlock) expand_kernel(const int64_t *__restrict__ offsets, int64_t n_rays,
                                                         const int32_t *__restrict__ nruns, RunReader rd, Lattice lat,
                                                         int64_t capacity, int32_t *__restrict__ ray_ids,
-                                                        float *__restrict__ t0, float *__restrict__ t1) {
-    expand_wave(offsets, n_rays, nruns, rd, OneLattice{lat}, capacity, ray_ids, t0, t1);
+                                                        float *__restrict__ t0, float *__restrict__ t1, int vec4) {
+    expand_block(offsets, n_rays, nruns, rd, OneLattice{lat}, capacity, ray_ids, t0, t1,
+                 vec4 != 0);
 }
 
 // Growing-step lattice, one thread: t_0 = near, t_{k+1} = fl(t_k +
@@ -232,7 +233,7 @@ Lattice make_lattice(float near_t, float far_t, const ogv_step *step, void *ws, 
 }
 
 size_t lds_bytes(const GridView &g) {
-    return g.kind == 1 ? tree_lds_bytes(g.L, g.NR, g.W) : 0;
+    return g.kind == 1 ? tree_lds_bytes(g.L, g.NR, g.S) : 0;
 }
 
 constexpr size_t kLdsTreeBytes = 32768;
@@ -371,7 +372,8 @@ ogv_status fill_all(const ogv_grid *grid, int32_t variant, const float *o, const
         return OGV_OK;
     }
     unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
-    expand_kernel<<<blocks, kBlock, 0, s>>>(offsets, n, b.nruns, reader_of(b), lat, cap, ids, t0, t1);
+    const int vec4 = (((uintptr_t)ids | (uintptr_t)t0 | (uintptr_t)t1) & 15) == 0;
+    expand_kernel<<<blocks, kBlock, 0, s>>>(offsets, n, b.nruns, reader_of(b), lat, cap, ids, t0, t1, vec4);
     OGV_CHECK_LAUNCH();
     dispatch_fill(grid->view, variant, o, d, n, lat, offsets, cap, ids, t0, t1, nullptr, b.pool.lost, b.pool.n_lost,
                   s);

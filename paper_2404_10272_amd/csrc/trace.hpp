@@ -65,55 +65,43 @@ struct DenseCursor {
     }
 };
 
-// The parts of a VDB tree a walk reads; root table and node masks may be
-// staged in LDS (when they fit), leaves are read from global memory.
+// The parts of a VDB tree a walk reads: the root table and the nodes' slot
+// tables (staged in LDS when they fit), and the leaves (global memory).
 struct Tree {
     const int32_t *root;
-    const uint64_t *child, *value;
-    const uint32_t *rank;
+    const int32_t *slot;
     const uint64_t *leaves;
-    int ilog2, S, NR, W;
+    int ilog2, S, NR;
 };
 
-__host__ __device__ inline size_t tree_lds_bytes(int L, int NR, int W) {
-    size_t n_root = (size_t)L * NR * NR * NR;
-    return n_root * (size_t)W * (8 + 8 + 4) + n_root * 4;
+__host__ __device__ inline size_t tree_lds_bytes(int L, int NR, int S) {
+    const size_t n_root = (size_t)L * NR * NR * NR;
+    return n_root * 4 + n_root * (size_t)S * S * S * 4;
 }
 
 // Every thread of the block must call this (it synchronizes).
 template <bool kLds>
-__device__ __forceinline__ Tree load_tree(const GridView &g, uint64_t *smem) {
+__device__ __forceinline__ Tree load_tree(const GridView &g, uint32_t *smem) {
     Tree t;
     t.ilog2 = g.ilog2;
     t.S = g.S;
     t.NR = g.NR;
-    t.W = g.W;
     t.leaves = g.leaves;
     if (!kLds) {
         t.root = g.root;
-        t.child = g.child;
-        t.value = g.value;
-        t.rank = g.rank;
+        t.slot = g.slot;
         return t;
     }
     // node slots exist for every root cell (the worst case the build sizes for)
     const int n_root = g.L * g.NR * g.NR * g.NR;
-    const int nw = n_root * g.W;
-    uint64_t *child = smem;
-    uint64_t *value = smem + nw;
-    uint32_t *rank = (uint32_t *)(smem + 2 * nw);
-    int32_t *root = (int32_t *)(rank + nw);
-    for (int i = threadIdx.x; i < nw; i += blockDim.x) {
-        child[i] = g.child[i];
-        value[i] = g.value[i];
-        rank[i] = g.rank[i];
-    }
+    const int ns = n_root * g.S * g.S * g.S;
+    int32_t *slot = (int32_t *)smem;
+    int32_t *root = slot + ns;
+    for (int i = threadIdx.x; i < ns; i += blockDim.x) slot[i] = g.slot[i];
     for (int i = threadIdx.x; i < n_root; i += blockDim.x) root[i] = g.root[i];
     __syncthreads();
     t.root = root;
-    t.child = child;
-    t.value = value;
-    t.rank = rank;
+    t.slot = slot;
     return t;
 }
 
@@ -160,15 +148,13 @@ struct VdbCursor {
             }
             const int m = t.S - 1;
             const int s = (((v0 >> 3) & m) * t.S + ((v1 >> 3) & m)) * t.S + ((v2 >> 3) & m);
-            const int w = node * t.W + (s >> 6);
-            const uint64_t cm = t.child[w];
-            const uint64_t bit = 1ull << (s & 63);
-            if (!(cm & bit)) {
-                o = (t.value[w] & bit) != 0;
+            const int c = t.slot[node * t.S * t.S * t.S + s];
+            if (c < 0) {
+                o = c == -2;
                 return 8;
             }
             lblk = blk;
-            lbase = (int)(t.rank[w] + (uint32_t)__popcll(cm & (bit - 1))) * 8;
+            lbase = c * 8;
             wx = -1;
         }
         if ((v0 & 7) != wx) {
@@ -588,12 +574,23 @@ __device__ __forceinline__ void trace_ray(const GridView &g, const Tree &tree, c
 
 // ------------------------------------------------------------------ expansion fill
 
-// Expansion fill: one wave per 64 consecutive rays.  Each lane loads its
-// ray's output offset, run count and first two runs in one round trip; the
-// wave then walks its rays in order (their values read out of the lanes as
-// wave-uniform scalars) and writes every run's samples with consecutive lanes
-// on consecutive outputs, so stores are contiguous and no lane searches for
-// its run.  Rays whose runs were lost are left to the traversal fill.
+// Expansion fill: a block takes 256 consecutive rays and writes their output
+// range [offsets[r0], offsets[r0 + 256]) with consecutive lanes on consecutive
+// 4-output groups (full-wave 16-byte stores).  The rays' kept runs are staged
+// in LDS in output order with block-relative first outputs; a ray whose runs
+// were lost contributes one placeholder run over its outputs, which the
+// traversal fill writes instead, so the runs tile the outputs without gaps.
+// The owner of every group comes from a map built per window of groups:
+// each run marks the group holding its first output with its index (LDS
+// max), and a block-wide max-scan then names, for every group, the last run
+// starting at or before its last output.  A lane reads its group's owner and
+// looks back over at most three earlier runs; there is no per-output search.
+// Block-relative offsets fit in 32 bits: a ray has at most 2^24 lattice
+// points, so 256 rays stay below 2^32 outputs.
+constexpr int kExpandRuns = 1024;     // runs staged per pass
+constexpr int kExpandGroups = 1024;   // 4-output groups per owner window
+constexpr int kGroupsPerLane = kExpandGroups / kBlock;
+
 struct OneLattice {       // every ray on one lattice
     Lattice lat;
     __device__ __forceinline__ int scene_of(int64_t) const { return 0; }
@@ -619,76 +616,172 @@ struct RunReader {
     const int32_t *chunk_next;
 };
 
-__device__ __forceinline__ int64_t lane_value(int64_t x, int i) {
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, i);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)x >> 32), i);
-    return (int64_t)(((uint64_t)hi << 32) | lo);
+__device__ __forceinline__ int64_t block_incl_scan256(int64_t x, int64_t *lds, int64_t &total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int64_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) lds[wid] = x;
+    __syncthreads();
+    int64_t base = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        int64_t v = lds[w];
+        if (w < wid) base += v;
+        total += v;
+    }
+    __syncthreads();
+    return base + x;   // inclusive
 }
 
 template <class Lats>
-__device__ __forceinline__ void expand_wave(const int64_t *__restrict__ offsets, int64_t n_rays,
-                                            const int32_t *__restrict__ nruns, const RunReader &rd,
-                                            const Lats &lats, int64_t capacity, int32_t *__restrict__ ray_ids,
-                                            float *__restrict__ t0, float *__restrict__ t1) {
-    const int lane = threadIdx.x & 63;
-    const int64_t r0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x - lane);   // the wave's first ray
-    if (r0 >= n_rays) return;                                                   // wave-uniform
-    const int64_t r = r0 + lane;
-    int64_t off = 0;
-    int nr = 0, sc = 0;
-    int2 ra = make_int2(0, 0), rb = make_int2(0, 0);
+__device__ __forceinline__ void expand_block(const int64_t *__restrict__ offsets, int64_t n_rays,
+                                             const int32_t *__restrict__ nruns, const RunReader &rd,
+                                             const Lats &lats, int64_t capacity, int32_t *__restrict__ ray_ids,
+                                             float *__restrict__ t0, float *__restrict__ t1, bool vec4) {
+    __shared__ uint32_t s_start[kExpandRuns + 1];   // [cn] bounds the last run of the pass
+    __shared__ uint32_t s_bn[kExpandRuns];          // n0 - start (mod 2^32): output j has lattice index s_bn + j
+    __shared__ int32_t s_ray[kExpandRuns];          // -1: placeholder of a lost ray
+    __shared__ int16_t s_scene[kExpandRuns];
+    __shared__ uint32_t s_own[kExpandGroups];       // 1 + owner run of each group of the window
+    __shared__ uint32_t s_wmax[kBlock / 64];
+    __shared__ int64_t s_wave[kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t r = r0 + threadIdx.x;
+    const int64_t base = offsets[r0];
+    const int64_t bend = offsets[min(r0 + kBlock, n_rays)];
+    if (min(bend, capacity) <= base) return;   // block-uniform: nothing to write
+    const uint32_t end_rel = (uint32_t)(bend - base);
+    const uint32_t lim_rel = (uint32_t)(min(bend, capacity) - base);
+    int nr = 0, scene = 0;
+    bool lost = false;
+    uint32_t start = 0, lost_len = 0;
     if (r < n_rays) {
-        off = offsets[r];
+        const int64_t off = offsets[r];
+        start = (uint32_t)(off - base);
         nr = nruns[r];
-        sc = lats.scene_of(r);
-        if (nr != kRunsLost && nr > 0) ra = rd.slots[r * kMaxRuns];
-        if (nr != kRunsLost && nr > 1) rb = rd.slots[r * kMaxRuns + 1];
-    }
-    const int m = (int)min((int64_t)64, n_rays - r0);
-    for (int i = 0; i < m; ++i) {
-        const int nri = __builtin_amdgcn_readlane(nr, i);
-        if (nri == kRunsLost || nri == 0) continue;
-        int64_t pos = lane_value(off, i);
-        if (pos >= capacity) break;   // offsets never decrease: no later ray fits either
-        const int si = __builtin_amdgcn_readlane(sc, i);
-        const int64_t ray = r0 + i;
-        int32_t chunk = -1;
-        for (int k = 0; k < nri; ++k) {
-            int2 run;
-            if (k == 0) {
-                run = make_int2(__builtin_amdgcn_readlane(ra.x, i), __builtin_amdgcn_readlane(ra.y, i));
-            } else if (k == 1) {
-                run = make_int2(__builtin_amdgcn_readlane(rb.x, i), __builtin_amdgcn_readlane(rb.y, i));
-            } else if (k < kMaxRuns) {
-                run = rd.slots[ray * kMaxRuns + k];
-            } else {
-                if (k % kMaxRuns == 0) chunk = k == kMaxRuns ? rd.ray_next[ray] : rd.chunk_next[chunk];
-                run = rd.chunks[(int64_t)chunk * kMaxRuns + k % kMaxRuns];
-            }
-            const int len = run.y - run.x;
-            // uniform bases, 32-bit lane offsets; the constant-step loop holds no
-            // load, so its stores are never made to wait for one another
-            const int lim = (int)min((int64_t)len, capacity - pos);
-            int32_t *__restrict__ oid = ray_ids + pos;
-            float *__restrict__ o0 = t0 + pos;
-            float *__restrict__ o1 = t1 + pos;
-            const Lattice L = lats.get(si);
-            if (!L.cone) {
-                for (int c = lane; c < lim; c += 64) {
-                    oid[c] = (int32_t)ray;
-                    o0[c] = L.t(run.x + c);
-                    o1[c] = L.t(run.x + c + 1);
-                }
-            } else {
-                for (int c = lane; c < lim; c += 64) {
-                    const float a = L.tab[run.x + c], b = L.tab[run.x + c + 1];
-                    oid[c] = (int32_t)ray;
-                    o0[c] = a;
-                    o1[c] = b;
-                }
-            }
-            pos += len;
+        if (nr == kRunsLost) {
+            lost = true;
+            lost_len = (uint32_t)(offsets[r + 1] - off);
+            nr = lost_len > 0 ? 1 : 0;
         }
+        scene = lats.scene_of(r);
+    }
+    int64_t total;
+    const int rb = (int)(block_incl_scan256((int64_t)nr, s_wave, total) - nr);
+    for (int c0 = 0; c0 < (int)total; c0 += kExpandRuns) {
+        const int cn = min((int)total - c0, kExpandRuns);
+        // stage runs c0 .. c0+cn-1; slot cn takes the next pass's first start
+        uint32_t st = start;
+        int32_t chunk = -1;
+        for (int k = 0; k < nr; ++k) {
+            int2 rn = make_int2(0, (int)lost_len);
+            if (!lost) {
+                if (k < kMaxRuns) {
+                    rn = rd.slots[r * kMaxRuns + k];
+                } else {
+                    if (k % kMaxRuns == 0) chunk = k == kMaxRuns ? rd.ray_next[r] : rd.chunk_next[chunk];
+                    rn = rd.chunks[(int64_t)chunk * kMaxRuns + k % kMaxRuns];
+                }
+            }
+            const int idx = rb + k - c0;
+            if (idx >= 0 && idx <= cn) s_start[idx] = st;
+            if (idx >= 0 && idx < cn) {
+                s_bn[idx] = (uint32_t)rn.x - st;
+                s_ray[idx] = lost ? -1 : (int32_t)r;
+                s_scene[idx] = (int16_t)scene;
+            }
+            st += (uint32_t)(rn.y - rn.x);
+        }
+        if (threadIdx.x == 0 && c0 + cn == (int)total) s_start[cn] = end_rel;
+        __syncthreads();
+        const uint32_t lo = s_start[0];
+        const uint32_t hi = min(s_start[cn], lim_rel);
+        if (hi > lo) {
+            // absolute groups of 4 outputs covering [base + lo, base + hi)
+            const int64_t g_first = (base + lo) >> 2, g_last = (base + hi - 1) >> 2;
+            uint32_t carry = 0;
+            for (int64_t gw = g_first; gw <= g_last; gw += kExpandGroups) {
+                const int nwin = (int)min((int64_t)kExpandGroups, g_last - gw + 1);
+                for (int i = threadIdx.x; i < kExpandGroups; i += kBlock) s_own[i] = 0;
+                __syncthreads();
+                for (int a = threadIdx.x; a < cn; a += kBlock) {
+                    const int64_t g = ((base + s_start[a]) >> 2) - gw;
+                    if (g >= 0 && g < nwin) atomicMax(&s_own[g], (uint32_t)(a + 1));
+                }
+                __syncthreads();
+                // block-wide inclusive max-scan of s_own, seeded with the carry
+                uint32_t v[kGroupsPerLane];
+                uint32_t m = 0;
+#pragma unroll
+                for (int e = 0; e < kGroupsPerLane; ++e) {
+                    m = max(m, s_own[kGroupsPerLane * threadIdx.x + e]);
+                    v[e] = m;
+                }
+                uint32_t incl = m;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const uint32_t y = __shfl_up(incl, off, 64);
+                    if (lane >= off) incl = max(incl, y);
+                }
+                if (lane == 63) s_wmax[wid] = incl;
+                __syncthreads();
+                uint32_t pre = carry;
+                for (int w = 0; w < wid; ++w) pre = max(pre, s_wmax[w]);
+                const uint32_t below = __shfl_up(incl, 1, 64);
+                if (lane > 0) pre = max(pre, below);
+#pragma unroll
+                for (int e = 0; e < kGroupsPerLane; ++e) s_own[kGroupsPerLane * threadIdx.x + e] = max(pre, v[e]);
+                __syncthreads();
+                carry = s_own[nwin - 1];
+                // each lane writes groups k = tid, tid + 256, ... of the window
+                for (int k = threadIdx.x; k < nwin; k += kBlock) {
+                    const int a = (int)s_own[k] - 1;             // owns the group's last output
+                    const int64_t j4 = 4 * (gw + k) - base;       // block-relative, may lie below lo
+                    // runs a-1, a-2, a-3 may own the group's earlier outputs
+                    const uint32_t sa = s_start[a];
+                    const uint32_t sb = a >= 1 ? s_start[a - 1] : 0u;
+                    const uint32_t sc = a >= 2 ? s_start[a - 2] : 0u;
+                    int32_t id[4];
+                    float x0[4], x1[4];
+                    bool ok[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int64_t j = j4 + q;
+                        ok[q] = j >= (int64_t)lo && j < (int64_t)hi;
+                        const uint32_t ju = (uint32_t)j;
+                        const int aq = a - (int)(sa > ju) - (int)(a >= 1 && sb > ju) - (int)(a >= 2 && sc > ju);
+                        const int b = ok[q] ? aq : a;
+                        id[q] = s_ray[b];
+                        ok[q] = ok[q] && id[q] >= 0;
+                        const Lattice L = lats.get(s_scene[b]);
+                        const int n = (int)(s_bn[b] + ju);
+                        x0[q] = ok[q] ? L.t(n) : 0.0f;
+                        x1[q] = ok[q] ? L.t(n + 1) : 0.0f;
+                    }
+                    const int64_t at = base + j4;
+                    if (vec4 && ok[0] && ok[1] && ok[2] && ok[3]) {
+                        *reinterpret_cast<int4 *>(ray_ids + at) = make_int4(id[0], id[1], id[2], id[3]);
+                        *reinterpret_cast<float4 *>(t0 + at) = make_float4(x0[0], x0[1], x0[2], x0[3]);
+                        *reinterpret_cast<float4 *>(t1 + at) = make_float4(x1[0], x1[1], x1[2], x1[3]);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (ok[q]) {
+                                ray_ids[at + q] = id[q];
+                                t0[at + q] = x0[q];
+                                t1[at + q] = x1[q];
+                            }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
     }
 }
 
