@@ -585,11 +585,15 @@ __device__ __forceinline__ void trace_ray(const GridView &g, const Tree &tree, c
 // max), and a block-wide max-scan then names, for every group, the last run
 // starting at or before its last output.  A lane reads its group's owner and
 // looks back over at most three earlier runs; there is no per-output search.
+// Marks carry the window's number in their high bits, so the map is cleared
+// once per block: entries left by earlier windows are never larger than the
+// owner carried into the current one.
 // Block-relative offsets fit in 32 bits: a ray has at most 2^24 lattice
 // points, so 256 rays stay below 2^32 outputs.
 constexpr int kExpandRuns = 1024;     // runs staged per pass
-constexpr int kExpandGroups = 1024;   // 4-output groups per owner window
+constexpr int kExpandGroups = 2048;   // 4-output groups per owner window
 constexpr int kGroupsPerLane = kExpandGroups / kBlock;
+constexpr int kOwnerBits = 11;        // owner entries: window number << 11 | (1 + run), run < 1024
 
 struct OneLattice {       // every ray on one lattice
     Lattice lat;
@@ -671,8 +675,10 @@ __device__ __forceinline__ void expand_block(const int64_t *__restrict__ offsets
         }
         scene = lats.scene_of(r);
     }
+    for (int i = threadIdx.x; i < kExpandGroups; i += kBlock) s_own[i] = 0;
     int64_t total;
     const int rb = (int)(block_incl_scan256((int64_t)nr, s_wave, total) - nr);
+    uint32_t epoch = 0;   // window number within the block
     for (int c0 = 0; c0 < (int)total; c0 += kExpandRuns) {
         const int cn = min((int)total - c0, kExpandRuns);
         // stage runs c0 .. c0+cn-1; slot cn takes the next pass's first start
@@ -707,11 +713,10 @@ __device__ __forceinline__ void expand_block(const int64_t *__restrict__ offsets
             uint32_t carry = 0;
             for (int64_t gw = g_first; gw <= g_last; gw += kExpandGroups) {
                 const int nwin = (int)min((int64_t)kExpandGroups, g_last - gw + 1);
-                for (int i = threadIdx.x; i < kExpandGroups; i += kBlock) s_own[i] = 0;
-                __syncthreads();
+                const uint32_t tag = ++epoch << kOwnerBits;
                 for (int a = threadIdx.x; a < cn; a += kBlock) {
                     const int64_t g = ((base + s_start[a]) >> 2) - gw;
-                    if (g >= 0 && g < nwin) atomicMax(&s_own[g], (uint32_t)(a + 1));
+                    if (g >= 0 && g < nwin) atomicMax(&s_own[g], tag | (uint32_t)(a + 1));
                 }
                 __syncthreads();
                 // block-wide inclusive max-scan of s_own, seeded with the carry
@@ -740,7 +745,7 @@ __device__ __forceinline__ void expand_block(const int64_t *__restrict__ offsets
                 carry = s_own[nwin - 1];
                 // each lane writes groups k = tid, tid + 256, ... of the window
                 for (int k = threadIdx.x; k < nwin; k += kBlock) {
-                    const int a = (int)s_own[k] - 1;             // owns the group's last output
+                    const int a = (int)(s_own[k] & ((1u << kOwnerBits) - 1)) - 1;   // owns the group's last output
                     const int64_t j4 = 4 * (gw + k) - base;       // block-relative, may lie below lo
                     // runs a-1, a-2, a-3 may own the group's earlier outputs
                     const uint32_t sa = s_start[a];
