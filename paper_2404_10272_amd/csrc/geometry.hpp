@@ -73,16 +73,18 @@ struct Axis {
     }
 
     // Advance ray-order voxel u (known to satisfy Tk(u) <= t) to the
-    // voxel owning the parameters just after t, without passing u_hi.
+    // voxel owning the parameters just after t, without passing u_hi: the
+    // largest e in [u, u_hi] with Tk(e) <= t, by binary search on the exact
+    // crossings (they never decrease along the ray).  Needs no position
+    // estimate, so a walk keeps no estimate inputs live for it.
     __device__ __forceinline__ int advance_to(int u, float t, int u_hi) const {
-        float p = o + t * d;
-        float vf = floorf((p - B) * inv_h);
-        float uf = pos ? vf : (float)(R - 1) - vf;
-        uf = fminf(fmaxf(uf, (float)u), (float)u_hi);
-        int e = (int)uf;
-        while (e > u && !(Tk(e) <= t)) --e;
-        while (e < u_hi && Tk(e + 1) <= t) ++e;
-        return e;
+        int lo = u, hi = u_hi;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (Tk(mid) <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
     }
 };
 

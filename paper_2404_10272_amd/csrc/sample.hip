@@ -85,12 +85,12 @@ __global__ void pool_reset_kernel(int32_t *head) {
         head[1] = 0;
     }
 }
+
 __global__ void __launch_bounds__(kBlock) expand_kernel(const int64_t *__restrict__ offsets, int64_t n_rays,
                                                         const int32_t *__restrict__ nruns, RunReader rd, Lattice lat,
                                                         int64_t capacity, int32_t *__restrict__ ray_ids,
                                                         float *__restrict__ t0, float *__restrict__ t1, int vec4) {
-    expand_block(offsets, n_rays, nruns, rd, OneLattice{lat}, capacity, ray_ids, t0, t1,
-                 vec4 != 0);
+    expand_block(offsets, n_rays, nruns, rd, OneLattice{lat}, capacity, ray_ids, t0, t1, vec4 != 0);
 }
 
 // Growing-step lattice, one thread: t_0 = near, t_{k+1} = fl(t_k +
@@ -254,7 +254,8 @@ Bufs bufs_of(void *ws, const Plan &p) {
     b.pool.ray_next = (int32_t *)(w + p.off_next);
     b.pool.chunks = (int2 *)(w + p.off_chunks);
     b.pool.chunk_next = (int32_t *)(w + p.off_cnext);
-    b.pool.head = (int32_t *)(w + p.off_ntab) + 1;   // [0] n_tab, [1] pool head, [2] lost rays
+    // [0] n_tab, [1] pool head, [2] lost rays
+    b.pool.head = (int32_t *)(w + p.off_ntab) + 1;
     b.pool.cap = p.pool_cap;
     b.pool.lost = (int32_t *)(w + p.off_lost);
     b.pool.n_lost = (int32_t *)(w + p.off_ntab) + 2;
