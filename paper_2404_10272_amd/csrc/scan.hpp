@@ -1,5 +1,6 @@
-// Device-wide exclusive scan of int32 values into int64 offsets (reduce,
-// scan of tile sums, apply), used for per-ray sample offsets and for leaf
+// Device-wide exclusive scan of int32 values into int64 offsets (reduce per
+// tile, then apply with each tile's base; a separate scan of the tile sums
+// only for very long inputs), used for per-ray sample offsets and for leaf
 // and node numbering when a VDB tree is built.
 #pragma once
 
@@ -101,6 +102,44 @@ __global__ void __launch_bounds__(kScanThreads) scan_apply_kernel(const int32_t 
     }
 }
 
+// Apply with the tile's base summed in place from the raw tile sums (no
+// separate scan of the tile sums); the last tile also writes the total and
+// the overflow flag.  For up to kScanDirectTiles tiles.
+constexpr int64_t kScanDirectTiles = 4096;
+
+__global__ void __launch_bounds__(kScanThreads) scan_apply_direct_kernel(const int32_t *__restrict__ counts, int64_t n,
+                                                                        const int64_t *__restrict__ tile_sums,
+                                                                        int64_t *__restrict__ offsets,
+                                                                        int64_t capacity,
+                                                                        int32_t *__restrict__ overflow) {
+    __shared__ int64_t lds[kScanThreads / 64];
+    int64_t before = 0;
+    for (int64_t k = threadIdx.x; k < (int64_t)blockIdx.x; k += kScanThreads) before += tile_sums[k];
+    int64_t tile_base;
+    block_excl_scan(before, lds, tile_base);   // block total = sum of the earlier tiles
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int32_t c[kScanItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = base + j;
+        c[j] = i < n ? counts[i] : 0;
+        s += c[j];
+    }
+    int64_t total;
+    int64_t ex = block_excl_scan(s, lds, total) + tile_base;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = base + j;
+        if (i < n) offsets[i] = ex;
+        ex += c[j];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        offsets[n] = tile_base + total;
+        if (overflow) *overflow = tile_base + total > capacity ? 1 : 0;
+    }
+}
+
 // out[0..n-1] = exclusive scan of in, out[n] = total; tiles needs
 // scan_tiles(n) + 1 int64 of scratch.  overflow (nullable) <- total > capacity.
 inline int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
@@ -108,6 +147,11 @@ inline int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
 inline hipError_t launch_excl_scan(const int32_t *in, int64_t n, int64_t *out, int64_t *tiles, int64_t capacity,
                                    int32_t *overflow, hipStream_t s) {
     int64_t nt = scan_tiles(n);
+    if (nt > 0 && nt <= kScanDirectTiles) {
+        scan_reduce_kernel<<<(unsigned)nt, kScanThreads, 0, s>>>(in, n, tiles);
+        scan_apply_direct_kernel<<<(unsigned)nt, kScanThreads, 0, s>>>(in, n, tiles, out, capacity, overflow);
+        return hipGetLastError();
+    }
     if (nt > 0) scan_reduce_kernel<<<(unsigned)nt, kScanThreads, 0, s>>>(in, n, tiles);
     scan_tiles_kernel<<<1, kScanThreads, 0, s>>>(tiles, nt, out + n, capacity, overflow);
     if (nt > 0) scan_apply_kernel<<<(unsigned)nt, kScanThreads, 0, s>>>(in, n, tiles, out);

@@ -644,7 +644,7 @@ __device__ __forceinline__ int64_t block_incl_scan256(int64_t x, int64_t *lds, i
 }
 
 template <class Lats>
-__device__ __forceinline__ void expand_block(const int64_t *__restrict__ offsets, int64_t n_rays,
+__device__ __forceinline__ void expand_chunk(int64_t r0, const int64_t *__restrict__ offsets, int64_t n_rays,
                                              const int32_t *__restrict__ nruns, const RunReader &rd,
                                              const Lats &lats, int64_t capacity, int32_t *__restrict__ ray_ids,
                                              float *__restrict__ t0, float *__restrict__ t1, bool vec4) {
@@ -656,7 +656,6 @@ __device__ __forceinline__ void expand_block(const int64_t *__restrict__ offsets
     __shared__ uint32_t s_wmax[kBlock / 64];
     __shared__ int64_t s_wave[kBlock / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int64_t r0 = (int64_t)blockIdx.x * kBlock;
     const int64_t r = r0 + threadIdx.x;
     const int64_t base = offsets[r0];
     const int64_t bend = offsets[min(r0 + kBlock, n_rays)];
@@ -790,6 +789,17 @@ __device__ __forceinline__ void expand_block(const int64_t *__restrict__ offsets
         }
         __syncthreads();
     }
+}
+
+// The grid strides over 256-ray chunks, so a launch may use fewer blocks than
+// chunks (every chunk ends on a barrier, so its LDS is free for the next).
+template <class Lats>
+__device__ __forceinline__ void expand_block(const int64_t *__restrict__ offsets, int64_t n_rays,
+                                             const int32_t *__restrict__ nruns, const RunReader &rd,
+                                             const Lats &lats, int64_t capacity, int32_t *__restrict__ ray_ids,
+                                             float *__restrict__ t0, float *__restrict__ t1, bool vec4) {
+    for (int64_t r0 = (int64_t)blockIdx.x * kBlock; r0 < n_rays; r0 += (int64_t)gridDim.x * kBlock)
+        expand_chunk(r0, offsets, n_rays, nruns, rd, lats, capacity, ray_ids, t0, t1, vec4);
 }
 
 // ------------------------------------------------------------------ ray order
