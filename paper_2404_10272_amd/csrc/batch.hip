@@ -215,7 +215,7 @@ hipError_t enqueue_pass(ogv_batch *b, int64_t *offsets, int64_t capacity, int32_
     e = launch_excl_scan(b->counts, b->n_total, offsets, b->tiles, capacity, overflow, s);
     if (e != hipSuccess || capacity == 0) return e;
     unsigned blocks = (unsigned)((b->n_total + kBlock - 1) / kBlock);
-    const RunReader rd{b->pool.slots, b->pool.ray_next, b->pool.chunks, b->pool.chunk_next};
+    const RunReader rd{b->pool.slots, b->pool.stride, b->pool.ray_next, b->pool.chunks, b->pool.chunk_next};
     const int vec4 = (((uintptr_t)ids | (uintptr_t)t0 | (uintptr_t)t1) & 15) == 0;
     batch_expand_kernel<<<blocks, kBlock, 0, s>>>(offsets, b->n_total, b->nruns, rd, b->lats_dev, b->first_dev,
                                                   b->n_scenes, capacity, ids, t0, t1, vec4);
@@ -347,6 +347,7 @@ extern "C" ogv_status ogv_batch_create(const ogv_scene *scenes, int32_t n, int32
     b->counts = (int32_t *)(m + o_counts);
     b->nruns = (int32_t *)(m + o_nruns);
     b->pool.slots = (int2 *)(m + o_runs);
+    b->pool.stride = total;
     b->pool.ray_next = (int32_t *)(m + o_next);
     b->pool.chunks = (int2 *)(m + o_chunks);
     b->pool.chunk_next = (int32_t *)(m + o_cnext);

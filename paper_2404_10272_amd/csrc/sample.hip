@@ -251,6 +251,7 @@ Bufs bufs_of(void *ws, const Plan &p) {
     b.counts = (int32_t *)(w + p.off_counts);
     b.nruns = (int32_t *)(w + p.off_nruns);
     b.pool.slots = (int2 *)(w + p.off_runs);
+    b.pool.stride = p.n_rays;
     b.pool.ray_next = (int32_t *)(w + p.off_next);
     b.pool.chunks = (int2 *)(w + p.off_chunks);
     b.pool.chunk_next = (int32_t *)(w + p.off_cnext);
@@ -264,7 +265,7 @@ Bufs bufs_of(void *ws, const Plan &p) {
 }
 
 RunReader reader_of(const Bufs &b) {
-    return RunReader{b.pool.slots, b.pool.ray_next, b.pool.chunks, b.pool.chunk_next};
+    return RunReader{b.pool.slots, b.pool.stride, b.pool.ray_next, b.pool.chunks, b.pool.chunk_next};
 }
 
 template <bool kVdb, bool kSkip, bool kLds>

@@ -309,7 +309,8 @@ constexpr int kMaxRuns = 16;
 constexpr int32_t kRunsLost = 0x7fffffff;
 
 struct RunPool {
-    int2 *slots;          // [rays][kMaxRuns]
+    int2 *slots;          // [kMaxRuns][stride]: slot k of ray r at k * stride + r (reads of one slot coalesce)
+    int64_t stride;       // rays the slot array is laid out for
     int32_t *ray_next;    // [rays]: first pool chunk of the ray, -1 if none
     int2 *chunks;         // [cap][kMaxRuns]
     int32_t *chunk_next;  // [cap]
@@ -338,7 +339,7 @@ struct CountVis {
         if (nr == kRunsLost) return;
         const int j = nr % kMaxRuns;
         if (nr < kMaxRuns) {
-            pool.slots[ray * kMaxRuns + nr] = make_int2(a, b);
+            pool.slots[(int64_t)nr * pool.stride + ray] = make_int2(a, b);
         } else {
             if (j == 0) {
                 int32_t c = atomicAdd(pool.head, 1);
@@ -616,7 +617,8 @@ struct SceneLattices {    // ray r on the lattice of its scene
 };
 
 struct RunReader {
-    const int2 *slots;
+    const int2 *slots;    // [kMaxRuns][stride]
+    int64_t stride;
     const int32_t *ray_next;
     const int2 *chunks;
     const int32_t *chunk_next;
@@ -682,14 +684,20 @@ __device__ __forceinline__ void expand_chunk(int64_t r0, const int64_t *__restri
     uint32_t epoch = 0;   // window number within the block
     for (int c0 = 0; c0 < (int)total; c0 += kExpandRuns) {
         const int cn = min((int)total - c0, kExpandRuns);
-        // stage runs c0 .. c0+cn-1; slot cn takes the next pass's first start
+        // stage runs c0 .. c0+cn-1; slot cn takes the next pass's first start.
+        // Slots 0 and 1 (most rays have at most two runs) are fetched up
+        // front with independent loads that coalesce across the wave.
         uint32_t st = start;
         int32_t chunk = -1;
+        const int2 *sp = rd.slots + r;
+        int2 r0v = make_int2(0, (int)lost_len), r1v = make_int2(0, 0);
+        if (!lost && nr > 0) r0v = sp[0];
+        if (!lost && nr > 1) r1v = sp[rd.stride];
         for (int k = 0; k < nr; ++k) {
-            int2 rn = make_int2(0, (int)lost_len);
-            if (!lost) {
+            int2 rn = k == 0 ? r0v : r1v;
+            if (!lost && k >= 2) {
                 if (k < kMaxRuns) {
-                    rn = rd.slots[r * kMaxRuns + k];
+                    rn = sp[(int64_t)k * rd.stride];
                 } else {
                     if (k % kMaxRuns == 0) chunk = k == kMaxRuns ? rd.ray_next[r] : rd.chunk_next[chunk];
                     rn = rd.chunks[(int64_t)chunk * kMaxRuns + k % kMaxRuns];

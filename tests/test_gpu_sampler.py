@@ -316,3 +316,22 @@ def test_split_count_matches_count_and_fills_the_same(obj):
     e = torch.zeros((0, 3), device="cuda")
     empty.count_raw(e, e)
     assert empty.scan().cpu().tolist() == [0]
+
+
+def test_offsets_of_many_rays_take_the_long_scan(small):
+    # 4099 copies of the small workload's 4096 rays: 16.8 M rays, more than
+    # the 4096 scan tiles the two-launch scan handles, so the three-launch
+    # path runs; offsets must be the running sum of the oracle's per-ray
+    # counts, repeated
+    ref = oracle.sample_counts(oracle.Scene(small.occ, small.boxes), small.origins, small.dirs, small.near,
+                               small.far, small.step, "dense_branch")
+    reps = (1 << 24) // small.n_rays + 3
+    n = reps * small.n_rays
+    o = torch.from_numpy(small.origins).cuda().repeat(reps, 1)
+    d = torch.from_numpy(small.dirs).cuda().repeat(reps, 1)
+    g = gpu_grid("vdb", small.occ, small.boxes, small.ilog2)
+    sp = api.Sampler(g, n, small.near, small.far, api.make_step(small.step), "branch")
+    got = sp.count(o, d).cpu().numpy()
+    want = np.concatenate([[0], np.cumsum(np.tile(np.asarray(ref, np.int64), reps))])
+    np.testing.assert_array_equal(got, want)
+    del sp, o, d
