@@ -72,8 +72,8 @@ class Timed:
         self.t1 = torch.empty(self.S, dtype=torch.float32, device="cuda")
 
     def step(self, ev=None):
-        # count = walk (pool reset + count kernel) then scan; fill = expansion
-        # (+ the traversal fill of lost rays, an empty launch when none are)
+        # count = walk (pool reset + count kernel, which also sums the scan
+        # tiles) then scan (one apply launch); fill = expansion (one launch)
         if ev is not None:
             ev[0].record()
         self.sp.count_raw(self.o, self.d)
@@ -279,7 +279,7 @@ def main():
         dom = {"kernel": "count_kernel", "stage": "walk: pool reset + count_kernel (VDB, hierarchical DDA)",
                "bytes": walk_bytes, "ms": walk_ms}
     else:
-        dom = {"kernel": "expand_kernel", "stage": "fill: expand_kernel + lost-ray traversal fill (empty launch)",
+        dom = {"kernel": "expand_kernel", "stage": "fill: expand_kernel (kept runs, then lost rays re-walked)",
                "bytes": fill_bytes, "ms": fill_ms}
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
 

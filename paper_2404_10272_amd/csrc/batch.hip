@@ -99,21 +99,14 @@ __global__ void __launch_bounds__(kBlock) batch_count_kernel(const SceneDesc *__
     }
 }
 
-__global__ void __launch_bounds__(kBlock) batch_expand_kernel(const int64_t *__restrict__ offsets, int64_t n_total,
-                                                              const int32_t *__restrict__ nruns, RunReader rd,
-                                                              const Lattice *__restrict__ lats,
-                                                              const int64_t *__restrict__ first, int n_scenes,
-                                                              int64_t capacity, int32_t *__restrict__ ray_ids,
-                                                              float *__restrict__ t0, float *__restrict__ t1, int vec4) {
-    expand_block(offsets, n_total, nruns, rd, SceneLattices{lats, first, n_scenes}, capacity, ray_ids, t0, t1,
-                 vec4 != 0);
-}
-
+// Traversal fill of the rays whose runs were lost, each on its scene's grid
+// and lattice; the blocks of the launch stride through the list.
 template <bool kSkip>
-__global__ void __launch_bounds__(kBlock) batch_overflow_fill_kernel(
-    const SceneDesc *__restrict__ scenes, int n_scenes, const int32_t *__restrict__ lost,
-    const int32_t *__restrict__ n_lost, const int64_t *__restrict__ offsets, int64_t capacity,
-    int32_t *__restrict__ ray_ids, float *__restrict__ t0, float *__restrict__ t1) {
+__device__ __forceinline__ void batch_fill_lost(const SceneDesc *__restrict__ scenes, int n_scenes,
+                                                const int32_t *__restrict__ lost, const int32_t *__restrict__ n_lost,
+                                                const int64_t *__restrict__ offsets, int64_t capacity,
+                                                int32_t *__restrict__ ray_ids, float *__restrict__ t0,
+                                                float *__restrict__ t1) {
     const int64_t m = *n_lost;
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < m; k += (int64_t)gridDim.x * kBlock) {
         const int64_t gr = lost[k];
@@ -134,6 +127,24 @@ __global__ void __launch_bounds__(kBlock) batch_overflow_fill_kernel(
         else trace_ray<false, kSkip>(g, tree, o, d, lat, vis, ctx);
     }
 }
+
+// Expansion of the kept runs, then, in the same launch, the traversal fill of
+// the lost rays (their outputs are disjoint from the expansion's).
+template <bool kSkip>
+__global__ void __launch_bounds__(kBlock) batch_expand_kernel(const int64_t *__restrict__ offsets, int64_t n_total,
+                                                              const int32_t *__restrict__ nruns, RunReader rd,
+                                                              const Lattice *__restrict__ lats,
+                                                              const int64_t *__restrict__ first, int n_scenes,
+                                                              int64_t capacity, int32_t *__restrict__ ray_ids,
+                                                              float *__restrict__ t0, float *__restrict__ t1, int vec4,
+                                                              const SceneDesc *__restrict__ scenes,
+                                                              const int32_t *__restrict__ lost,
+                                                              const int32_t *__restrict__ n_lost) {
+    expand_block(offsets, n_total, nruns, rd, SceneLattices{lats, first, n_scenes}, capacity, ray_ids, t0, t1,
+                 vec4 != 0);
+    batch_fill_lost<kSkip>(scenes, n_scenes, lost, n_lost, offsets, capacity, ray_ids, t0, t1);
+}
+
 
 // growing-step lattice of one scene (one thread), padded past its length
 __global__ void batch_cone_table_kernel(float tmin, float tmax, float cone, float dt_min, float *tab, int32_t cap) {
@@ -217,16 +228,14 @@ hipError_t enqueue_pass(ogv_batch *b, int64_t *offsets, int64_t capacity, int32_
     unsigned blocks = (unsigned)((b->n_total + kBlock - 1) / kBlock);
     const RunReader rd{b->pool.slots, b->pool.stride, b->pool.ray_next, b->pool.chunks, b->pool.chunk_next};
     const int vec4 = (((uintptr_t)ids | (uintptr_t)t0 | (uintptr_t)t1) & 15) == 0;
-    batch_expand_kernel<<<blocks, kBlock, 0, s>>>(offsets, b->n_total, b->nruns, rd, b->lats_dev, b->first_dev,
-                                                  b->n_scenes, capacity, ids, t0, t1, vec4);
-    // rays whose runs were lost (rare): a small grid strides through their list
-    const unsigned lblocks = std::min(blocks, 64u);
     if (b->variant == OGV_SKIP)
-        batch_overflow_fill_kernel<true><<<lblocks, kBlock, 0, s>>>(b->desc_dev, b->n_scenes, b->pool.lost,
-                                                                    b->pool.n_lost, offsets, capacity, ids, t0, t1);
+        batch_expand_kernel<true><<<blocks, kBlock, 0, s>>>(offsets, b->n_total, b->nruns, rd, b->lats_dev,
+                                                            b->first_dev, b->n_scenes, capacity, ids, t0, t1, vec4,
+                                                            b->desc_dev, b->pool.lost, b->pool.n_lost);
     else
-        batch_overflow_fill_kernel<false><<<lblocks, kBlock, 0, s>>>(b->desc_dev, b->n_scenes, b->pool.lost,
-                                                                     b->pool.n_lost, offsets, capacity, ids, t0, t1);
+        batch_expand_kernel<false><<<blocks, kBlock, 0, s>>>(offsets, b->n_total, b->nruns, rd, b->lats_dev,
+                                                             b->first_dev, b->n_scenes, capacity, ids, t0, t1, vec4,
+                                                             b->desc_dev, b->pool.lost, b->pool.n_lost);
     return hipGetLastError();
 }
 

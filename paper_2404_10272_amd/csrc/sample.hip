@@ -25,26 +25,51 @@ namespace ogv {
 // ------------------------------------------------------------------ kernels
 
 
+// The wave adds its rays' counts to the sums of the scan tiles (kScanTile
+// consecutive rays each) it touches: one wave reduction and one atomic per
+// tile, so the scan needs no reduce launch of its own.
+__device__ __forceinline__ void add_tile_sums(int64_t ray, int32_t n, int64_t *__restrict__ tile_sums) {
+    const int lane = threadIdx.x & 63;
+    const int32_t key = ray >= 0 ? (int32_t)(ray / kScanTile) : -1;
+    uint64_t todo = __ballot(key >= 0);
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int32_t k = __shfl(key, leader, 64);
+        const bool mine = key == k;
+        int32_t v = mine ? n : 0;   // a wave's 64 rays hold < 2^31 samples (2^24 lattice points each)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == leader) atomicAdd((unsigned long long *)&tile_sums[k], (unsigned long long)(int64_t)v);
+        todo &= ~__ballot(mine);
+    }
+}
+
 // counts[i] = samples of ray i; nruns[i] = its occupied runs (kRunsLost: the
 // run pool ran dry, the traversal fill writes the ray); the runs themselves
-// go to the pool's slots and chunks.
+// go to the pool's slots and chunks; tile_sums[k] gains the counts of rays
+// k*kScanTile .. (k+1)*kScanTile-1.
 template <bool kVdb, bool kSkip, bool kLds, bool kL1>
 __global__ void __launch_bounds__(kBlock) count_kernel(GridView g, const float *__restrict__ origins,
                                                        const float *__restrict__ dirs, int64_t n_rays, Lattice lat,
                                                        int32_t *__restrict__ counts, int32_t *__restrict__ nruns,
-                                                       RunPool pool, int image_width) {
+                                                       RunPool pool, int image_width,
+                                                       int64_t *__restrict__ tile_sums) {
     extern __shared__ uint32_t smem[];
     Tree tree = kVdb ? load_tree<kLds>(g, smem) : Tree{};
     const int64_t i = ray_of_thread((int64_t)blockIdx.x * kBlock + threadIdx.x, n_rays, image_width);
-    if (i < 0) return;
-    float o[3], d[3];
-    load_ray(origins, dirs, i, o, d);
-    const CountCtx ctx{lat, pool};
-    CountVis vis = make_count_vis(i, pool);
-    trace_ray<kVdb, kSkip, kL1>(g, tree, o, d, lat, vis, ctx);
-    vis.finish(ctx);
-    counts[i] = vis.n;
-    nruns[i] = vis.nr;
+    int32_t n = 0;
+    if (i >= 0) {
+        float o[3], d[3];
+        load_ray(origins, dirs, i, o, d);
+        const CountCtx ctx{lat, pool};
+        CountVis vis = make_count_vis(i, pool);
+        trace_ray<kVdb, kSkip, kL1>(g, tree, o, d, lat, vis, ctx);
+        vis.finish(ctx);
+        n = vis.n;
+        counts[i] = n;
+        nruns[i] = vis.nr;
+    }
+    add_tile_sums(i, n, tile_sums);
 }
 
 // Traversal fill: re-walks rays and writes their samples from offsets[i]:
@@ -78,19 +103,48 @@ __global__ void __launch_bounds__(kBlock) fill_kernel(GridView g, const float *_
     }
 }
 
-// zeroes the pool head and the lost-ray count (head[0], head[1])
-__global__ void pool_reset_kernel(int32_t *head) {
+// zeroes the pool head and the lost-ray count (head[0], head[1]) and the
+// scan tile sums the count pass accumulates
+__global__ void pool_reset_kernel(int32_t *head, int64_t *tile_sums, int64_t n_tiles) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         head[0] = 0;
         head[1] = 0;
     }
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_tiles; k += (int64_t)gridDim.x * blockDim.x)
+        tile_sums[k] = 0;
 }
 
-__global__ void __launch_bounds__(kBlock) expand_kernel(const int64_t *__restrict__ offsets, int64_t n_rays,
+// Expansion of the kept runs, then, in the same launch, the traversal fill
+// of the rays whose runs the pool could not hold: after the expansion the
+// blocks stride through their list, reading the tree from global memory.
+// Those outputs are disjoint from the expansion's (it skips them, and a
+// 16-byte group they share is written with 4-byte stores).
+template <bool kVdb, bool kSkip>
+__global__ void __launch_bounds__(kBlock) expand_kernel(GridView g, const float *__restrict__ origins,
+                                                        const float *__restrict__ dirs,
+                                                        const int64_t *__restrict__ offsets, int64_t n_rays,
                                                         const int32_t *__restrict__ nruns, RunReader rd, Lattice lat,
                                                         int64_t capacity, int32_t *__restrict__ ray_ids,
-                                                        float *__restrict__ t0, float *__restrict__ t1, int vec4) {
+                                                        float *__restrict__ t0, float *__restrict__ t1, int vec4,
+                                                        const int32_t *__restrict__ lost,
+                                                        const int32_t *__restrict__ n_lost) {
     expand_block(offsets, n_rays, nruns, rd, OneLattice{lat}, capacity, ray_ids, t0, t1, vec4 != 0);
+    const int64_t m = *n_lost;
+    if (m == 0) return;
+    const Tree tree = kVdb ? load_tree<false>(g, nullptr) : Tree{};
+    const FillCtx ctx{lat, capacity, ray_ids, t0, t1, nullptr, g.R};
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < m; k += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = lost[k];
+        const int64_t first = offsets[i];
+        if (first >= capacity) continue;
+        float o[3], d[3];
+        load_ray(origins, dirs, i, o, d);
+        FillVis<false> vis;
+        vis.idx = first;
+        vis.ray = (int32_t)i;
+        vis.lev = 0;
+        trace_ray<kVdb, kSkip>(g, tree, o, d, lat, vis, ctx);
+    }
 }
 
 // Growing-step lattice, one thread: t_0 = near, t_{k+1} = fl(t_k +
@@ -273,13 +327,14 @@ void launch_count(const GridView &g, const float *o, const float *d, int64_t n, 
                   int width, hipStream_t s) {
     unsigned blocks = (unsigned)((tiled_threads(n, width) + kBlock - 1) / kBlock);
     size_t shm = kLds ? lds_bytes(g) : 0;
-    pool_reset_kernel<<<1, 64, 0, s>>>(b.pool.head);
+    const int64_t nt = scan_tiles(n);
+    pool_reset_kernel<<<(unsigned)std::min<int64_t>((nt + 255) / 256 + 1, 64), 256, 0, s>>>(b.pool.head, b.tiles, nt);
     if (g.L == 1)
         count_kernel<kVdb, kSkip, kLds, true>
-            <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool, width);
+            <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool, width, b.tiles);
     else
         count_kernel<kVdb, kSkip, kLds, false>
-            <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool, width);
+            <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool, width, b.tiles);
 }
 
 // Lost-ray fills run on a small grid that strides through the list.
@@ -356,7 +411,7 @@ ogv_status count_and_scan(const ogv_grid *grid, int32_t variant, int width, cons
     Bufs b = bufs_of(ws, p);
     dispatch_count(grid->view, variant, o, d, n, lat, b, width, s);
     OGV_CHECK_LAUNCH();
-    OGV_CHECK_HIP(launch_excl_scan(b.counts, n, offsets, b.tiles, capacity, overflow, s));
+    OGV_CHECK_HIP(launch_excl_scan_from_sums(b.counts, n, offsets, b.tiles, capacity, overflow, s));
     return OGV_OK;
 }
 
@@ -375,10 +430,18 @@ ogv_status fill_all(const ogv_grid *grid, int32_t variant, const float *o, const
     }
     unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
     const int vec4 = (((uintptr_t)ids | (uintptr_t)t0 | (uintptr_t)t1) & 15) == 0;
-    expand_kernel<<<blocks, kBlock, 0, s>>>(offsets, n, b.nruns, reader_of(b), lat, cap, ids, t0, t1, vec4);
-    OGV_CHECK_LAUNCH();
-    dispatch_fill(grid->view, variant, o, d, n, lat, offsets, cap, ids, t0, t1, nullptr, b.pool.lost, b.pool.n_lost,
-                  s);
+    const GridView &g = grid->view;
+#define OGV_EXPAND(V, K)                                                                                            \
+    expand_kernel<V, K><<<blocks, kBlock, 0, s>>>(g, o, d, offsets, n, b.nruns, reader_of(b), lat, cap, ids, t0, t1, \
+                                                   vec4, b.pool.lost, b.pool.n_lost)
+    if (g.kind == 0) {
+        if (variant == OGV_SKIP) OGV_EXPAND(false, true);
+        else OGV_EXPAND(false, false);
+    } else {
+        if (variant == OGV_SKIP) OGV_EXPAND(true, true);
+        else OGV_EXPAND(true, false);
+    }
+#undef OGV_EXPAND
     OGV_CHECK_LAUNCH();
     return OGV_OK;
 }
@@ -460,7 +523,7 @@ extern "C" ogv_status ogv_sample_scan(int64_t n, int64_t *offsets, void *ws, siz
         return OGV_OK;
     }
     Bufs b = bufs_of(ws, p);
-    OGV_CHECK_HIP(launch_excl_scan(b.counts, n, offsets, b.tiles, 0, nullptr, s));
+    OGV_CHECK_HIP(launch_excl_scan_from_sums(b.counts, n, offsets, b.tiles, 0, nullptr, s));
     return OGV_OK;
 }
 

@@ -158,5 +158,19 @@ inline hipError_t launch_excl_scan(const int32_t *in, int64_t n, int64_t *out, i
     return hipGetLastError();
 }
 
+// As launch_excl_scan, for a producer that has already left each tile's sum
+// of `in` in tiles[0 .. scan_tiles(n)-1]: up to kScanDirectTiles tiles one
+// apply launch reads them (and leaves them intact, so the scan can be
+// repeated); longer inputs take the full three launches.
+inline hipError_t launch_excl_scan_from_sums(const int32_t *in, int64_t n, int64_t *out, int64_t *tiles,
+                                             int64_t capacity, int32_t *overflow, hipStream_t s) {
+    int64_t nt = scan_tiles(n);
+    if (nt > 0 && nt <= kScanDirectTiles) {
+        scan_apply_direct_kernel<<<(unsigned)nt, kScanThreads, 0, s>>>(in, n, tiles, out, capacity, overflow);
+        return hipGetLastError();
+    }
+    return launch_excl_scan(in, n, out, tiles, capacity, overflow, s);
+}
+
 }  // namespace
 }  // namespace ogv

@@ -300,8 +300,10 @@ def test_split_count_matches_count_and_fills_the_same(obj):
         sp.offsets.fill_(-7)
         sp.count_raw(o, d)
         split = sp.scan().clone()
+        again = sp.scan().clone()   # the scan leaves the count's tile sums intact
         torch.cuda.synchronize()
         assert torch.equal(whole, split), kind
+        assert torch.equal(split, again), kind
         S = int(split[-1].item())
         ids = torch.empty(S, dtype=torch.int32, device="cuda")
         t0 = torch.empty(S, device="cuda")
@@ -334,4 +336,5 @@ def test_offsets_of_many_rays_take_the_long_scan(small):
     got = sp.count(o, d).cpu().numpy()
     want = np.concatenate([[0], np.cumsum(np.tile(np.asarray(ref, np.int64), reps))])
     np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(sp.scan().cpu().numpy(), want)   # a repeated scan agrees
     del sp, o, d
