@@ -9,8 +9,8 @@
 //   dL/dsigma_i = dt_i (g_C . (T_{i+1} c_i - sum_{k>i} w_k c_k) + g_A T_n),
 // with the suffix sum accumulated in a reverse pass (not as C minus a
 // prefix) and T rebuilt from the exponent sum, whose absolute error stays
-// at the level of one rounding of the ray's total optical depth.  One wave
-// handles one ray, 64 consecutive samples at a time.
+// at the level of one rounding of the ray's total optical depth.  One 16-lane
+// row (a DPP row) handles one ray, 16 consecutive samples at a time.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -21,52 +21,57 @@ namespace ogv {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kRow = 16;                    // lanes per ray: one DPP row
+constexpr int kRaysPerBlock = kBlock / kRow;
 
-__device__ __forceinline__ float wave_incl_scan(float x, int lane) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        float y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
+// Row-local data movement on the VALU (DPP): lane j of a 16-lane row reads
+// lane j - n (row_shr) or j + n (row_shl) of the same row; lanes whose
+// source falls outside the row read 0.
+template <int kCtrl>
+__device__ __forceinline__ float dpp(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, 0xF, 0xF, true));
+}
+// inclusive prefix sum over the row (lane 15 ends with the row total)
+__device__ __forceinline__ float row_prefix(float x) {
+    x += dpp<0x111>(x);
+    x += dpp<0x112>(x);
+    x += dpp<0x114>(x);
+    x += dpp<0x118>(x);
     return x;
 }
-
-// inclusive scan from the high lanes down: lane i gets sum over lanes >= i
-__device__ __forceinline__ float wave_rev_incl_scan(float x, int lane) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        float y = __shfl_down(x, off, 64);
-        if (lane + off < 64) x += y;
-    }
+// inclusive suffix sum over the row (lane 0 ends with the row total)
+__device__ __forceinline__ float row_suffix(float x) {
+    x += dpp<0x101>(x);
+    x += dpp<0x102>(x);
+    x += dpp<0x104>(x);
+    x += dpp<0x108>(x);
     return x;
 }
-
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
+// value of lane `src` (0..15) of this lane's row
+__device__ __forceinline__ float row_lane(float x, int src) {
+    return __shfl(x, ((int)threadIdx.x & 63 & ~(kRow - 1)) | src, 64);
 }
 
-// One wave per ray: 64 consecutive samples per step (coalesced loads), the
-// optical depth before each sample by a wave prefix scan plus the running
-// carry of the earlier chunks.
+// One 16-lane row per ray, 16 consecutive samples per step (coalesced
+// loads); the optical depth before each sample is a row prefix sum plus the
+// carry of the earlier steps.  Rows past the last ray do nothing, but stay
+// in their wave so that every DPP source lane is active.
 __global__ void __launch_bounds__(kBlock) composite_fwd_kernel(const int64_t *__restrict__ offsets, int64_t n_rays,
                                                               const float *__restrict__ t0,
                                                               const float *__restrict__ t1,
                                                               const float *__restrict__ sigma,
                                                               const float *__restrict__ rgb, float *__restrict__ out_rgb,
                                                               float *__restrict__ out_opacity) {
-    const int lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (r >= n_rays) return;
-    const int64_t a = offsets[r], b = offsets[r + 1];
+    const int l = threadIdx.x & (kRow - 1);
+    const int64_t r = (int64_t)blockIdx.x * kRaysPerBlock + (threadIdx.x / kRow);
+    const bool live = r < n_rays;
+    const int64_t a = live ? offsets[r] : 0, b = live ? offsets[r + 1] : 0;
     float cr = 0.f, cg = 0.f, cb = 0.f, acc = 0.f, carry = 0.f;
-    for (int64_t base = a; base < b; base += 64) {
-        const int64_t i = base + lane;
+    for (int64_t base = a; base < b; base += kRow) {   // row-uniform
+        const int64_t i = base + l;
         const bool ok = i < b;
         const float tau = ok ? sigma[i] * (t1[i] - t0[i]) : 0.f;
-        const float incl = wave_incl_scan(tau, lane);
+        const float incl = row_prefix(tau);
         const float T = expf(-(carry + incl - tau));
         const float w = ok ? T * (-expm1f(-tau)) : 0.f;
         if (ok) {
@@ -75,13 +80,13 @@ __global__ void __launch_bounds__(kBlock) composite_fwd_kernel(const int64_t *__
             cb += w * rgb[3 * i + 2];
         }
         acc += w;
-        carry += __shfl(incl, 63, 64);
+        carry += row_lane(incl, kRow - 1);
     }
-    cr = wave_sum(cr);
-    cg = wave_sum(cg);
-    cb = wave_sum(cb);
-    acc = wave_sum(acc);
-    if (lane == 0) {
+    cr = row_prefix(cr);
+    cg = row_prefix(cg);
+    cb = row_prefix(cb);
+    acc = row_prefix(acc);
+    if (live && l == kRow - 1) {
         out_rgb[3 * r + 0] = cr;
         out_rgb[3 * r + 1] = cg;
         out_rgb[3 * r + 2] = cb;
@@ -89,33 +94,35 @@ __global__ void __launch_bounds__(kBlock) composite_fwd_kernel(const int64_t *__
     }
 }
 
-// One wave per ray.  Pass 1: the ray's total optical depth.  Pass 2, chunks
-// from the back: T_i and T_{i+1} from the total minus the depth at and after
-// i (reverse scan plus the carry of later chunks), and sum_{k>i} w_k c_k by a
-// reverse scan plus the carry -- never as C minus a prefix.
+// One 16-lane row per ray.  Pass 1: the ray's total optical depth.  Pass 2,
+// steps from the back: T_i and T_{i+1} from the total minus the depth at and
+// after i (row suffix sum plus the carry of later steps), and
+// sum_{k>i} w_k c_k by a row suffix sum plus the carry -- never as C minus a
+// prefix.
 __global__ void __launch_bounds__(kBlock) composite_bwd_kernel(
     const int64_t *__restrict__ offsets, int64_t n_rays, const float *__restrict__ t0, const float *__restrict__ t1,
     const float *__restrict__ sigma, const float *__restrict__ rgb, const float *__restrict__ g_rgb,
     const float *__restrict__ g_opacity, float *__restrict__ d_sigma, float *__restrict__ d_rgb) {
-    const int lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (r >= n_rays) return;
-    const int64_t a = offsets[r], b = offsets[r + 1];
-    if (a == b) return;
+    const int l = threadIdx.x & (kRow - 1);
+    const int64_t r = (int64_t)blockIdx.x * kRaysPerBlock + (threadIdx.x / kRow);
+    const bool live = r < n_rays;
+    const int64_t a = live ? offsets[r] : 0, b = live ? offsets[r + 1] : 0;
     float part = 0.f;
-    for (int64_t i = a + lane; i < b; i += 64) part += sigma[i] * (t1[i] - t0[i]);
-    const float total = wave_sum(part);
-    const float gr = g_rgb[3 * r + 0], gg = g_rgb[3 * r + 1], gb = g_rgb[3 * r + 2];
-    const float ga = g_opacity ? g_opacity[r] : 0.f;
+    for (int64_t i = a + l; i < b; i += kRow) part += sigma[i] * (t1[i] - t0[i]);
+    const float total = row_lane(row_prefix(part), kRow - 1);
+    const float gr = live ? g_rgb[3 * r + 0] : 0.f, gg = live ? g_rgb[3 * r + 1] : 0.f;
+    const float gb = live ? g_rgb[3 * r + 2] : 0.f;
+    const float ga = live && g_opacity ? g_opacity[r] : 0.f;
     const float T_end = expf(-total);
-    float after_tau = 0.f;                      // depth of the later chunks
-    float ar = 0.f, ag = 0.f, ab = 0.f;         // sum of w c over the later chunks
-    for (int64_t base = a + ((b - a - 1) / 64) * 64; base >= a; base -= 64) {
-        const int64_t i = base + lane;
+    float after_tau = 0.f;                      // depth of the later steps
+    float ar = 0.f, ag = 0.f, ab = 0.f;         // sum of w c over the later steps
+    for (int64_t base = a + ((b - a - 1) / kRow) * kRow; b > a && base >= a; base -= kRow) {   // row-uniform
+        const int64_t i = base + l;
         const bool ok = i < b;
         const float dt = ok ? t1[i] - t0[i] : 0.f;
         const float tau = ok ? sigma[i] * dt : 0.f;
-        const float sfx = wave_rev_incl_scan(tau, lane) + after_tau;   // depth at and after i
+        const float sfx_row = row_suffix(tau);
+        const float sfx = sfx_row + after_tau;   // depth at and after i
         const float T_here = expf(-(total - sfx));
         const float T_next = expf(-(total - (sfx - tau)));
         const float w = ok ? T_here * (-expm1f(-tau)) : 0.f;
@@ -126,9 +133,10 @@ __global__ void __launch_bounds__(kBlock) composite_bwd_kernel(
             cb = rgb[3 * i + 2];
         }
         const float wr = w * cr, wg = w * cg, wb = w * cb;
-        const float sr = wave_rev_incl_scan(wr, lane) - wr + ar;   // sum over k > i
-        const float sg = wave_rev_incl_scan(wg, lane) - wg + ag;
-        const float sb = wave_rev_incl_scan(wb, lane) - wb + ab;
+        const float qr = row_suffix(wr), qg = row_suffix(wg), qb = row_suffix(wb);
+        const float sr = qr - wr + ar;   // sum over k > i
+        const float sg = qg - wg + ag;
+        const float sb = qb - wb + ab;
         if (ok) {
             const float dC = gr * (T_next * cr - sr) + gg * (T_next * cg - sg) + gb * (T_next * cb - sb);
             d_sigma[i] = dt * (dC + ga * T_end);
@@ -136,10 +144,10 @@ __global__ void __launch_bounds__(kBlock) composite_bwd_kernel(
             d_rgb[3 * i + 1] = w * gg;
             d_rgb[3 * i + 2] = w * gb;
         }
-        after_tau += wave_sum(tau);
-        ar += wave_sum(wr);
-        ag += wave_sum(wg);
-        ab += wave_sum(wb);
+        after_tau += row_lane(sfx_row, 0);
+        ar += row_lane(qr, 0);
+        ag += row_lane(qg, 0);
+        ab += row_lane(qb, 0);
     }
 }
 
@@ -155,7 +163,7 @@ extern "C" ogv_status ogv_composite_fwd(const int64_t *offsets, int64_t n_rays, 
     if (n_rays == 0) return OGV_OK;
     if (!offsets || !out_rgb || !t0 || !t1 || !sigma || !rgb) OGV_FAIL(OGV_ERR_INVALID, "null argument");
     hipStream_t s = (hipStream_t)stream;
-    const unsigned blocks = (unsigned)((n_rays + kWavesPerBlock - 1) / kWavesPerBlock);
+    const unsigned blocks = (unsigned)((n_rays + kRaysPerBlock - 1) / kRaysPerBlock);
     composite_fwd_kernel<<<blocks, kBlock, 0, s>>>(offsets, n_rays, t0, t1, sigma, rgb, out_rgb, out_opacity);
     OGV_CHECK_LAUNCH();
     return OGV_OK;
@@ -169,7 +177,7 @@ extern "C" ogv_status ogv_composite_bwd(const int64_t *offsets, int64_t n_rays, 
     if (!offsets || !t0 || !t1 || !sigma || !rgb || !g_rgb || !d_sigma || !d_rgb)
         OGV_FAIL(OGV_ERR_INVALID, "null argument");
     hipStream_t s = (hipStream_t)stream;
-    const unsigned blocks = (unsigned)((n_rays + kWavesPerBlock - 1) / kWavesPerBlock);
+    const unsigned blocks = (unsigned)((n_rays + kRaysPerBlock - 1) / kRaysPerBlock);
     composite_bwd_kernel<<<blocks, kBlock, 0, s>>>(offsets, n_rays, t0, t1, sigma, rgb, g_rgb, g_opacity, d_sigma,
                                                    d_rgb);
     OGV_CHECK_LAUNCH();
