@@ -130,8 +130,11 @@ def composite_side(api, torch, scenes, hdda, N, steps):
     g_a = torch.ones(N, device="cuda")
     fwd = time_events(torch, lambda: api.composite_forward(off, hdda.t0, hdda.t1, sig, col), steps, 2)
     bwd = time_events(torch, lambda: api.composite_backward(off, hdda.t0, hdda.t1, sig, col, g_rgb, g_a), steps, 2)
-    fb = 20 * S + 8 * N + 16 * N            # samples read, offsets read, pixels written
-    bb = 2 * 20 * S + 8 * N + 16 * N + 16 * S
+    # algorithmic bytes: each sample's t0, t1, sigma, rgb read once (24 B), offsets read,
+    # per-ray rgb + opacity written (forward) or read as gradients (backward), and the
+    # backward's d_sigma, d_rgb written (16 B per sample)
+    fb = 24 * S + 8 * (N + 1) + 16 * N
+    bb = 24 * S + 8 * (N + 1) + 16 * N + 16 * S
     return {"forward_ms": fwd, "backward_ms": bwd, "forward_GBps": fb / (fwd * 1e-3) / 1e9,
             "backward_GBps": bb / (bwd * 1e-3) / 1e9, "samples": S}
 

@@ -10,7 +10,7 @@
 // with the suffix sum accumulated in a reverse pass (not as C minus a
 // prefix) and T rebuilt from the exponent sum, whose absolute error stays
 // at the level of one rounding of the ray's total optical depth.  One 16-lane
-// row (a DPP row) handles one ray, 16 consecutive samples at a time.
+// row (a DPP row) handles one ray, 16 consecutive samples per chunk.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -52,9 +52,15 @@ __device__ __forceinline__ float row_lane(float x, int src) {
     return __shfl(x, ((int)threadIdx.x & 63 & ~(kRow - 1)) | src, 64);
 }
 
-// One 16-lane row per ray, 16 consecutive samples per step (coalesced
+// Samples of one row are loaded kGroup chunks of 16 at a time, all loads of a
+// group issued before any of its arithmetic, so that one memory latency
+// covers 64 samples instead of 16.
+constexpr int kGroup = 4;
+constexpr int kSpan = kGroup * kRow;
+
+// One 16-lane row per ray, 16 consecutive samples per chunk (coalesced
 // loads); the optical depth before each sample is a row prefix sum plus the
-// carry of the earlier steps.  Rows past the last ray do nothing, but stay
+// carry of the earlier chunks.  Rows past the last ray do nothing, but stay
 // in their wave so that every DPP source lane is active.
 __global__ void __launch_bounds__(kBlock) composite_fwd_kernel(const int64_t *__restrict__ offsets, int64_t n_rays,
                                                               const float *__restrict__ t0,
@@ -67,20 +73,31 @@ __global__ void __launch_bounds__(kBlock) composite_fwd_kernel(const int64_t *__
     const bool live = r < n_rays;
     const int64_t a = live ? offsets[r] : 0, b = live ? offsets[r + 1] : 0;
     float cr = 0.f, cg = 0.f, cb = 0.f, acc = 0.f, carry = 0.f;
-    for (int64_t base = a; base < b; base += kRow) {   // row-uniform
-        const int64_t i = base + l;
-        const bool ok = i < b;
-        const float tau = ok ? sigma[i] * (t1[i] - t0[i]) : 0.f;
-        const float incl = row_prefix(tau);
-        const float T = expf(-(carry + incl - tau));
-        const float w = ok ? T * (-expm1f(-tau)) : 0.f;
-        if (ok) {
-            cr += w * rgb[3 * i + 0];
-            cg += w * rgb[3 * i + 1];
-            cb += w * rgb[3 * i + 2];
+    for (int64_t g0 = a; g0 < b; g0 += kSpan) {   // row-uniform
+        float tau[kGroup], xr[kGroup], xg[kGroup], xb[kGroup];
+#pragma unroll
+        for (int c = 0; c < kGroup; ++c) {
+            const int64_t i = g0 + c * kRow + l;
+            tau[c] = xr[c] = xg[c] = xb[c] = 0.f;
+            if (i < b) {
+                tau[c] = sigma[i] * (t1[i] - t0[i]);
+                xr[c] = rgb[3 * i + 0];
+                xg[c] = rgb[3 * i + 1];
+                xb[c] = rgb[3 * i + 2];
+            }
         }
-        acc += w;
-        carry += row_lane(incl, kRow - 1);
+#pragma unroll
+        for (int c = 0; c < kGroup; ++c) {
+            if (g0 + c * kRow >= b) break;   // row-uniform
+            const float incl = row_prefix(tau[c]);
+            const float T = expf(-(carry + incl - tau[c]));
+            const float w = g0 + c * kRow + l < b ? T * (-expm1f(-tau[c])) : 0.f;
+            cr += w * xr[c];
+            cg += w * xg[c];
+            cb += w * xb[c];
+            acc += w;
+            carry += row_lane(incl, kRow - 1);
+        }
     }
     cr = row_prefix(cr);
     cg = row_prefix(cg);
@@ -94,11 +111,11 @@ __global__ void __launch_bounds__(kBlock) composite_fwd_kernel(const int64_t *__
     }
 }
 
-// One 16-lane row per ray.  Pass 1: the ray's total optical depth.  Pass 2,
-// steps from the back: T_i and T_{i+1} from the total minus the depth at and
-// after i (row suffix sum plus the carry of later steps), and
-// sum_{k>i} w_k c_k by a row suffix sum plus the carry -- never as C minus a
-// prefix.
+// One 16-lane row per ray.  Pass 1: the ray's total optical depth; its last
+// group of chunks stays in registers.  Pass 2, groups and chunks from the
+// back: T_i and T_{i+1} from the total minus the depth at and after i (row
+// suffix sum plus the carry of later chunks), and sum_{k>i} w_k c_k by a row
+// suffix sum plus the carry -- never as C minus a prefix.
 __global__ void __launch_bounds__(kBlock) composite_bwd_kernel(
     const int64_t *__restrict__ offsets, int64_t n_rays, const float *__restrict__ t0, const float *__restrict__ t1,
     const float *__restrict__ sigma, const float *__restrict__ rgb, const float *__restrict__ g_rgb,
@@ -107,47 +124,75 @@ __global__ void __launch_bounds__(kBlock) composite_bwd_kernel(
     const int64_t r = (int64_t)blockIdx.x * kRaysPerBlock + (threadIdx.x / kRow);
     const bool live = r < n_rays;
     const int64_t a = live ? offsets[r] : 0, b = live ? offsets[r + 1] : 0;
+    const int64_t last = b > a ? a + ((b - a - 1) / kSpan) * kSpan : a;   // first sample of the last group
+    float dt[kGroup], tau[kGroup], xr[kGroup], xg[kGroup], xb[kGroup];
+    auto load_group = [&](int64_t g0) {
+#pragma unroll
+        for (int c = 0; c < kGroup; ++c) {
+            const int64_t i = g0 + c * kRow + l;
+            dt[c] = tau[c] = xr[c] = xg[c] = xb[c] = 0.f;
+            if (i < b) {
+                dt[c] = t1[i] - t0[i];
+                tau[c] = sigma[i] * dt[c];
+                xr[c] = rgb[3 * i + 0];
+                xg[c] = rgb[3 * i + 1];
+                xb[c] = rgb[3 * i + 2];
+            }
+        }
+    };
+
     float part = 0.f;
-    for (int64_t i = a + l; i < b; i += kRow) part += sigma[i] * (t1[i] - t0[i]);
+    for (int64_t g0 = a; g0 < last; g0 += kSpan) {   // whole groups before the last
+        float q[kGroup];
+#pragma unroll
+        for (int c = 0; c < kGroup; ++c) {
+            const int64_t i = g0 + c * kRow + l;
+            q[c] = sigma[i] * (t1[i] - t0[i]);
+        }
+#pragma unroll
+        for (int c = 0; c < kGroup; ++c) part += q[c];
+    }
+    load_group(last);
+#pragma unroll
+    for (int c = 0; c < kGroup; ++c) part += tau[c];
     const float total = row_lane(row_prefix(part), kRow - 1);
+
     const float gr = live ? g_rgb[3 * r + 0] : 0.f, gg = live ? g_rgb[3 * r + 1] : 0.f;
     const float gb = live ? g_rgb[3 * r + 2] : 0.f;
     const float ga = live && g_opacity ? g_opacity[r] : 0.f;
     const float T_end = expf(-total);
-    float after_tau = 0.f;                      // depth of the later steps
-    float ar = 0.f, ag = 0.f, ab = 0.f;         // sum of w c over the later steps
-    for (int64_t base = a + ((b - a - 1) / kRow) * kRow; b > a && base >= a; base -= kRow) {   // row-uniform
-        const int64_t i = base + l;
-        const bool ok = i < b;
-        const float dt = ok ? t1[i] - t0[i] : 0.f;
-        const float tau = ok ? sigma[i] * dt : 0.f;
-        const float sfx_row = row_suffix(tau);
-        const float sfx = sfx_row + after_tau;   // depth at and after i
-        const float T_here = expf(-(total - sfx));
-        const float T_next = expf(-(total - (sfx - tau)));
-        const float w = ok ? T_here * (-expm1f(-tau)) : 0.f;
-        float cr = 0.f, cg = 0.f, cb = 0.f;
-        if (ok) {
-            cr = rgb[3 * i + 0];
-            cg = rgb[3 * i + 1];
-            cb = rgb[3 * i + 2];
+    float after_tau = 0.f;                      // depth of the later chunks
+    float ar = 0.f, ag = 0.f, ab = 0.f;         // sum of w c over the later chunks
+    for (int64_t g0 = last; g0 >= a; g0 -= kSpan) {   // row-uniform
+        if (g0 != last) load_group(g0);
+#pragma unroll
+        for (int c = kGroup - 1; c >= 0; --c) {
+            if (g0 + c * kRow >= b) continue;   // row-uniform
+            const int64_t i = g0 + c * kRow + l;
+            const bool ok = i < b;
+            const float sfx_row = row_suffix(tau[c]);
+            const float sfx = sfx_row + after_tau;   // depth at and after i
+            const float T_here = expf(-(total - sfx));
+            const float T_next = expf(-(total - (sfx - tau[c])));
+            const float w = ok ? T_here * (-expm1f(-tau[c])) : 0.f;
+            const float wr = w * xr[c], wg = w * xg[c], wb = w * xb[c];
+            const float qr = row_suffix(wr), qg = row_suffix(wg), qb = row_suffix(wb);
+            const float sr = qr - wr + ar;   // sum over k > i
+            const float sg = qg - wg + ag;
+            const float sb = qb - wb + ab;
+            if (ok) {
+                const float dC = gr * (T_next * xr[c] - sr) + gg * (T_next * xg[c] - sg) + gb * (T_next * xb[c] - sb);
+                d_sigma[i] = dt[c] * (dC + ga * T_end);
+                d_rgb[3 * i + 0] = w * gr;
+                d_rgb[3 * i + 1] = w * gg;
+                d_rgb[3 * i + 2] = w * gb;
+            }
+            after_tau += row_lane(sfx_row, 0);
+            ar += row_lane(qr, 0);
+            ag += row_lane(qg, 0);
+            ab += row_lane(qb, 0);
         }
-        const float wr = w * cr, wg = w * cg, wb = w * cb;
-        const float qr = row_suffix(wr), qg = row_suffix(wg), qb = row_suffix(wb);
-        const float sr = qr - wr + ar;   // sum over k > i
-        const float sg = qg - wg + ag;
-        const float sb = qb - wb + ab;
-        if (ok) {
-            const float dC = gr * (T_next * cr - sr) + gg * (T_next * cg - sg) + gb * (T_next * cb - sb);
-            d_sigma[i] = dt * (dC + ga * T_end);
-            d_rgb[3 * i + 0] = w * gr;
-            d_rgb[3 * i + 1] = w * gg;
-            d_rgb[3 * i + 2] = w * gb;
-        }
-        after_tau += row_lane(sfx_row, 0);
-        ar += row_lane(qr, 0);
-        ag += row_lane(qg, 0);
-        ab += row_lane(qb, 0);
+        if (g0 == a) break;
     }
 }
 
