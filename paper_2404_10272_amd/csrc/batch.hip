@@ -28,6 +28,7 @@ namespace ogv {
 namespace {
 
 constexpr int kMaxScenes = 64;
+static_assert(kMaxScenes <= kBlock, "the expansion stages every scene's lattice, one per thread");
 
 struct SceneDesc {
     GridView g;
@@ -131,7 +132,7 @@ __device__ __forceinline__ void batch_fill_lost(const SceneDesc *__restrict__ sc
 // Expansion of the kept runs, then, in the same launch, the traversal fill of
 // the lost rays (their outputs are disjoint from the expansion's).
 template <bool kSkip>
-__global__ void __launch_bounds__(kBlock) batch_expand_kernel(const int64_t *__restrict__ offsets, int64_t n_total,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kExpandWaves))) batch_expand_kernel(const int64_t *__restrict__ offsets, int64_t n_total,
                                                               const int32_t *__restrict__ nruns, RunReader rd,
                                                               const Lattice *__restrict__ lats,
                                                               const int64_t *__restrict__ first, int n_scenes,
@@ -225,7 +226,7 @@ hipError_t enqueue_pass(ogv_batch *b, int64_t *offsets, int64_t capacity, int32_
     if (e != hipSuccess) return e;
     e = launch_excl_scan(b->counts, b->n_total, offsets, b->tiles, capacity, overflow, s);
     if (e != hipSuccess || capacity == 0) return e;
-    unsigned blocks = (unsigned)((b->n_total + kBlock - 1) / kBlock);
+    const unsigned blocks = (unsigned)min(expand_items(b->n_total), (int64_t)INT32_MAX);
     const RunReader rd{b->pool.slots, b->pool.stride, b->pool.ray_next, b->pool.chunks, b->pool.chunk_next};
     const int vec4 = (((uintptr_t)ids | (uintptr_t)t0 | (uintptr_t)t1) & 15) == 0;
     if (b->variant == OGV_SKIP)

@@ -120,7 +120,7 @@ __global__ void pool_reset_kernel(int32_t *head, int64_t *tile_sums, int64_t n_t
 // Those outputs are disjoint from the expansion's (it skips them, and a
 // 16-byte group they share is written with 4-byte stores).
 template <bool kVdb, bool kSkip>
-__global__ void __launch_bounds__(kBlock) expand_kernel(GridView g, const float *__restrict__ origins,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kExpandWaves))) expand_kernel(GridView g, const float *__restrict__ origins,
                                                         const float *__restrict__ dirs,
                                                         const int64_t *__restrict__ offsets, int64_t n_rays,
                                                         const int32_t *__restrict__ nruns, RunReader rd, Lattice lat,
@@ -428,7 +428,7 @@ ogv_status fill_all(const ogv_grid *grid, int32_t variant, const float *o, const
         OGV_CHECK_LAUNCH();
         return OGV_OK;
     }
-    unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
+    const unsigned blocks = (unsigned)min(expand_items(n), (int64_t)INT32_MAX);
     const int vec4 = (((uintptr_t)ids | (uintptr_t)t0 | (uintptr_t)t1) & 15) == 0;
     const GridView &g = grid->view;
 #define OGV_EXPAND(V, K)                                                                                            \

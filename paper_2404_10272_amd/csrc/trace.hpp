@@ -588,24 +588,39 @@ __device__ __forceinline__ void trace_ray(const GridView &g, const Tree &tree, c
 // max), and a block-wide max-scan then names, for every group, the last run
 // starting at or before its last output.  A lane reads its group's owner and
 // looks back over at most three earlier runs; there is no per-output search.
-// Marks carry the window's number in their high bits, so the map is cleared
-// once per block: entries left by earlier windows are never larger than the
-// owner carried into the current one.
+// The run starting last before a window marks the window's first group, so
+// each window's map stands alone.  Marks carry the window's number in their
+// high bits, so the map is cleared once per chunk: entries left by earlier
+// windows are smaller than the current window's first mark.
+// The windows of a chunk (2048 groups each, counted from the chunk's first
+// group) are dealt round-robin to kExpandParts blocks, so a chunk dense with
+// samples does not run its windows one after another in one block while the
+// rest of the chip has finished.
 // Block-relative offsets fit in 32 bits: a ray has at most 2^24 lattice
 // points, so 256 rays stay below 2^32 outputs.
 constexpr int kExpandRuns = 1024;     // runs staged per pass
 constexpr int kExpandGroups = 2048;   // 4-output groups per owner window
+constexpr int kExpandParts = 4;       // blocks sharing one chunk's windows
+// Waves per SIMD asked of the expansion kernels: six blocks of 256 lanes per CU
+// (LDS allows six).  At the register budget this leaves (80 VGPRs) the
+// constant-step expansion keeps its loops free of spills; only the rarely
+// taken lost-ray traversal and growing-step path spill.  An expansion block
+// spends much of its life waiting on loads and barriers while the other
+// blocks' stores fill HBM, so residency is what keeps the writes flowing.
+constexpr int kExpandWaves = 6;
 constexpr int kGroupsPerLane = kExpandGroups / kBlock;
 constexpr int kOwnerBits = 11;        // owner entries: window number << 11 | (1 + run), run < 1024
 
 struct OneLattice {       // every ray on one lattice
+    static constexpr bool kMulti = false;
     Lattice lat;
     __device__ __forceinline__ int scene_of(int64_t) const { return 0; }
     __device__ __forceinline__ Lattice get(int) const { return lat; }
 };
 
 struct SceneLattices {    // ray r on the lattice of its scene
-    const Lattice *lats;
+    static constexpr bool kMulti = true;
+    const Lattice *lats;   // [n], n <= kBlock
     const int64_t *first;  // first global ray of each scene, [n + 1]
     int n;
     __device__ __forceinline__ int scene_of(int64_t r) const {
@@ -645,39 +660,58 @@ __device__ __forceinline__ int64_t block_incl_scan256(int64_t x, int64_t *lds, i
     return base + x;   // inclusive
 }
 
-template <class Lats>
-__device__ __forceinline__ void expand_chunk(int64_t r0, const int64_t *__restrict__ offsets, int64_t n_rays,
+// LDS of one expansion block, declared once per kernel so that the two
+// instantiations of expand_chunk share it.
+struct ExpandLds {
+    uint32_t start[kExpandRuns + 1];   // [cn] bounds the last run of the pass
+    uint32_t bn[kExpandRuns];          // n0 - start (mod 2^32): output j has lattice index bn + j
+    int32_t ray[kExpandRuns];          // -1: placeholder of a lost ray
+    int16_t scene[kExpandRuns];
+    uint32_t own[kExpandGroups];       // 1 + owner run of each group of the window
+    uint32_t wmax[kBlock / 64];
+    int64_t wave[kBlock / 64];
+};
+
+// kCone: some ray is on a growing-step lattice, whose points come from a table
+// in global memory.  Otherwise the write loop issues no load: a load there
+// would make every group wait for the stores of the one before (one counter
+// covers both on this architecture).
+template <bool kCone, class Lats>
+__device__ __forceinline__ void expand_chunk(ExpandLds &sh, const float2 *s_lat, int64_t r0, int part,
+                                             const int64_t *__restrict__ offsets, int64_t n_rays,
                                              const int32_t *__restrict__ nruns, const RunReader &rd,
                                              const Lats &lats, int64_t capacity, int32_t *__restrict__ ray_ids,
                                              float *__restrict__ t0, float *__restrict__ t1, bool vec4) {
-    __shared__ uint32_t s_start[kExpandRuns + 1];   // [cn] bounds the last run of the pass
-    __shared__ uint32_t s_bn[kExpandRuns];          // n0 - start (mod 2^32): output j has lattice index s_bn + j
-    __shared__ int32_t s_ray[kExpandRuns];          // -1: placeholder of a lost ray
-    __shared__ int16_t s_scene[kExpandRuns];
-    __shared__ uint32_t s_own[kExpandGroups];       // 1 + owner run of each group of the window
-    __shared__ uint32_t s_wmax[kBlock / 64];
-    __shared__ int64_t s_wave[kBlock / 64];
+    uint32_t *const s_start = sh.start, *const s_bn = sh.bn, *const s_own = sh.own, *const s_wmax = sh.wmax;
+    int32_t *const s_ray = sh.ray;
+    int16_t *const s_scene = sh.scene;
+    int64_t *const s_wave = sh.wave;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t r = r0 + threadIdx.x;
+    const bool in = r < n_rays;
+    // Every global load of the staging depends on r alone, so all of them are
+    // issued here together: one memory round trip (the chunk's bounds, the
+    // ray's offsets and run count, and its first two run slots, read whether
+    // or not the ray has them; the slot arrays have a column for every ray).
     const int64_t base = offsets[r0];
     const int64_t bend = offsets[min(r0 + kBlock, n_rays)];
-    if (min(bend, capacity) <= base) return;   // block-uniform: nothing to write
+    const int64_t rc = in ? r : n_rays - 1;   // lanes past the last ray load a valid one's
+    const int64_t off = offsets[rc], off_next = offsets[rc + 1];
+    const int nr_rc = nruns[rc];
+    const int nr_raw = in ? nr_rc : 0;
+    const int2 slot0 = rd.slots[rc], slot1 = rd.slots[rd.stride + rc];
+    const int64_t lim = min(bend, capacity);
+    if (lim <= base) return;   // block-uniform: nothing to write
+    const int64_t G0 = base >> 2;   // the chunk's first group; windows count from it
+    if ((((lim - 1) >> 2) - G0) / kExpandGroups < part) return;   // block-uniform: no window of this part
     const uint32_t end_rel = (uint32_t)(bend - base);
     const uint32_t lim_rel = (uint32_t)(min(bend, capacity) - base);
-    int nr = 0, scene = 0;
-    bool lost = false;
-    uint32_t start = 0, lost_len = 0;
-    if (r < n_rays) {
-        const int64_t off = offsets[r];
-        start = (uint32_t)(off - base);
-        nr = nruns[r];
-        if (nr == kRunsLost) {
-            lost = true;
-            lost_len = (uint32_t)(offsets[r + 1] - off);
-            nr = lost_len > 0 ? 1 : 0;
-        }
-        scene = lats.scene_of(r);
-    }
+    int nr = nr_raw, scene = 0;
+    const bool lost = nr_raw == kRunsLost;
+    const uint32_t start = in ? (uint32_t)(off - base) : 0u;
+    const uint32_t lost_len = lost ? (uint32_t)(off_next - off) : 0u;
+    if (lost) nr = lost_len > 0 ? 1 : 0;
+    if (in) scene = lats.scene_of(r);
     for (int i = threadIdx.x; i < kExpandGroups; i += kBlock) s_own[i] = 0;
     int64_t total;
     const int rb = (int)(block_incl_scan256((int64_t)nr, s_wave, total) - nr);
@@ -685,14 +719,10 @@ __device__ __forceinline__ void expand_chunk(int64_t r0, const int64_t *__restri
     for (int c0 = 0; c0 < (int)total; c0 += kExpandRuns) {
         const int cn = min((int)total - c0, kExpandRuns);
         // stage runs c0 .. c0+cn-1; slot cn takes the next pass's first start.
-        // Slots 0 and 1 (most rays have at most two runs) are fetched up
-        // front with independent loads that coalesce across the wave.
         uint32_t st = start;
         int32_t chunk = -1;
         const int2 *sp = rd.slots + r;
-        int2 r0v = make_int2(0, (int)lost_len), r1v = make_int2(0, 0);
-        if (!lost && nr > 0) r0v = sp[0];
-        if (!lost && nr > 1) r1v = sp[rd.stride];
+        const int2 r0v = lost ? make_int2(0, (int)lost_len) : slot0, r1v = slot1;
         for (int k = 0; k < nr; ++k) {
             int2 rn = k == 0 ? r0v : r1v;
             if (!lost && k >= 2) {
@@ -719,16 +749,23 @@ __device__ __forceinline__ void expand_chunk(int64_t r0, const int64_t *__restri
         if (hi > lo) {
             // absolute groups of 4 outputs covering [base + lo, base + hi)
             const int64_t g_first = (base + lo) >> 2, g_last = (base + hi - 1) >> 2;
-            uint32_t carry = 0;
-            for (int64_t gw = g_first; gw <= g_last; gw += kExpandGroups) {
-                const int nwin = (int)min((int64_t)kExpandGroups, g_last - gw + 1);
+            // this part's windows that meet the pass: w = part, part + kExpandParts, ...
+            int64_t w = (g_first - G0) / kExpandGroups;
+            w += ((part - (int)(w % kExpandParts)) + kExpandParts) % kExpandParts;
+            for (; G0 + w * kExpandGroups <= g_last; w += kExpandParts) {
+                const int64_t gw = max(g_first, G0 + w * kExpandGroups);
+                const int nwin = (int)(min(g_last, G0 + (w + 1) * kExpandGroups - 1) - gw + 1);
                 const uint32_t tag = ++epoch << kOwnerBits;
                 for (int a = threadIdx.x; a < cn; a += kBlock) {
                     const int64_t g = ((base + s_start[a]) >> 2) - gw;
-                    if (g >= 0 && g < nwin) atomicMax(&s_own[g], tag | (uint32_t)(a + 1));
+                    if (g >= nwin) continue;
+                    // a run starting before the window marks group 0 if it is the last such run
+                    // (run 0 starts at or before gw, so group 0 always holds a mark of this window)
+                    if (g >= 0 || a + 1 == cn || ((base + s_start[a + 1]) >> 2) >= gw)
+                        atomicMax(&s_own[g > 0 ? g : 0], tag | (uint32_t)(a + 1));
                 }
                 __syncthreads();
-                // block-wide inclusive max-scan of s_own, seeded with the carry
+                // block-wide inclusive max-scan of s_own
                 uint32_t v[kGroupsPerLane];
                 uint32_t m = 0;
 #pragma unroll
@@ -744,14 +781,13 @@ __device__ __forceinline__ void expand_chunk(int64_t r0, const int64_t *__restri
                 }
                 if (lane == 63) s_wmax[wid] = incl;
                 __syncthreads();
-                uint32_t pre = carry;
-                for (int w = 0; w < wid; ++w) pre = max(pre, s_wmax[w]);
+                uint32_t pre = 0;
+                for (int q = 0; q < wid; ++q) pre = max(pre, s_wmax[q]);
                 const uint32_t below = __shfl_up(incl, 1, 64);
                 if (lane > 0) pre = max(pre, below);
 #pragma unroll
                 for (int e = 0; e < kGroupsPerLane; ++e) s_own[kGroupsPerLane * threadIdx.x + e] = max(pre, v[e]);
                 __syncthreads();
-                carry = s_own[nwin - 1];
                 // each lane writes groups k = tid, tid + 256, ... of the window
                 for (int k = threadIdx.x; k < nwin; k += kBlock) {
                     const int a = (int)(s_own[k] & ((1u << kOwnerBits) - 1)) - 1;   // owns the group's last output
@@ -772,10 +808,18 @@ __device__ __forceinline__ void expand_chunk(int64_t r0, const int64_t *__restri
                         const int b = ok[q] ? aq : a;
                         id[q] = s_ray[b];
                         ok[q] = ok[q] && id[q] >= 0;
-                        const Lattice L = lats.get(s_scene[b]);
                         const int n = (int)(s_bn[b] + ju);
-                        x0[q] = ok[q] ? L.t(n) : 0.0f;
-                        x1[q] = ok[q] ? L.t(n + 1) : 0.0f;
+                        if constexpr (kCone) {
+                            const Lattice L = lats.get(s_scene[b]);
+                            x0[q] = ok[q] ? L.t(n) : 0.0f;
+                            x1[q] = ok[q] ? L.t(n + 1) : 0.0f;
+                        } else {   // Lattice::t of a constant step, from LDS or the arguments
+                            float2 c;
+                            if constexpr (Lats::kMulti) c = s_lat[s_scene[b]];
+                            else c = make_float2(lats.lat.tmin, lats.lat.dt);
+                            x0[q] = ok[q] ? __fadd_rn(c.x, __fmul_rn((float)n, c.y)) : 0.0f;
+                            x1[q] = ok[q] ? __fadd_rn(c.x, __fmul_rn((float)(n + 1), c.y)) : 0.0f;
+                        }
                     }
                     const int64_t at = base + j4;
                     if (vec4 && ok[0] && ok[1] && ok[2] && ok[3]) {
@@ -799,15 +843,46 @@ __device__ __forceinline__ void expand_chunk(int64_t r0, const int64_t *__restri
     }
 }
 
-// The grid strides over 256-ray chunks, so a launch may use fewer blocks than
-// chunks (every chunk ends on a barrier, so its LDS is free for the next).
+// Work items are (256-ray chunk, part) pairs, kExpandParts per chunk, part
+// by part: item i is part i / chunks of chunk i % chunks.  Blocks go to the
+// XCDs round-robin, so this order gives every XCD an even share of part 0
+// (which every chunk with samples has) instead of sending all of it to the
+// XCDs whose index is a multiple of kExpandParts.  The grid strides over the
+// items, so a launch may use fewer blocks than items (every item ends on a
+// barrier or returns before its first one, so its LDS is free for the next).
+__host__ __device__ inline int64_t expand_items(int64_t n_rays) {
+    return (n_rays + kBlock - 1) / kBlock * kExpandParts;
+}
+
 template <class Lats>
 __device__ __forceinline__ void expand_block(const int64_t *__restrict__ offsets, int64_t n_rays,
                                              const int32_t *__restrict__ nruns, const RunReader &rd,
                                              const Lats &lats, int64_t capacity, int32_t *__restrict__ ray_ids,
                                              float *__restrict__ t0, float *__restrict__ t1, bool vec4) {
-    for (int64_t r0 = (int64_t)blockIdx.x * kBlock; r0 < n_rays; r0 += (int64_t)gridDim.x * kBlock)
-        expand_chunk(r0, offsets, n_rays, nruns, rd, lats, capacity, ray_ids, t0, t1, vec4);
+    __shared__ ExpandLds sh;
+    __shared__ float2 s_lat[Lats::kMulti ? kBlock : 1];   // (tmin, dt) of every scene
+    bool cone;
+    if constexpr (Lats::kMulti) {
+        bool c = false;
+        if ((int)threadIdx.x < lats.n) {
+            const Lattice L = lats.get(threadIdx.x);
+            s_lat[threadIdx.x] = make_float2(L.tmin, L.dt);
+            c = L.cone;
+        }
+        cone = __syncthreads_or(c) != 0;
+    } else {
+        cone = lats.lat.cone;
+    }
+    const int64_t chunks = (n_rays + kBlock - 1) / kBlock;
+    if (cone) {
+        for (int64_t it = blockIdx.x; it < chunks * kExpandParts; it += gridDim.x)
+            expand_chunk<true>(sh, s_lat, it % chunks * kBlock, (int)(it / chunks), offsets, n_rays, nruns, rd, lats,
+                               capacity, ray_ids, t0, t1, vec4);
+    } else {
+        for (int64_t it = blockIdx.x; it < chunks * kExpandParts; it += gridDim.x)
+            expand_chunk<false>(sh, s_lat, it % chunks * kBlock, (int)(it / chunks), offsets, n_rays, nruns, rd, lats,
+                                capacity, ray_ids, t0, t1, vec4);
+    }
 }
 
 // ------------------------------------------------------------------ ray order
