@@ -139,6 +139,25 @@ def composite_side(api, torch, scenes, hdda, N, steps):
             "backward_GBps": bb / (bwd * 1e-3) / 1e9, "samples": S}
 
 
+def cascades_side(api, torch, scenes, steps, warmup):
+    """Four nested 128^3 cascades over [-2^k, 2^k]^3, growing step (cone 1/256,
+    dt_min 1e-3, near 0.05, far 1e3), 1280x832 rays from inside the scene:
+    count + scan + fill with the VDB + hierarchical DDA and with the dense march."""
+    w = scenes.workload("unbounded")
+    occ = torch.from_numpy(w.occ).cuda()
+    o = torch.from_numpy(w.origins).cuda()
+    d = torch.from_numpy(w.dirs).cuda()
+    out = {"rays": w.n_rays, "levels": int(w.occ.shape[0])}
+    for name, grid in (("vdb", api.build_vdb(occ, w.boxes, w.ilog2)), ("dense", api.build_dense(occ, w.boxes))):
+        t = Timed(api, torch, grid, w, o, d, "branch", w.image[0])
+        ms, walk, scan, fill = t.run(steps, warmup)
+        out[name] = {"ms_per_step": ms, "walk_ms": walk, "scan_ms": scan, "fill_ms": fill,
+                     "rays_per_s": w.n_rays / (ms * 1e-3), "samples": t.S}
+        del t
+    out["speedup_vs_dense"] = out["dense"]["ms_per_step"] / out["vdb"]["ms_per_step"]
+    return out
+
+
 def batched_side(api, torch, scenes, steps):
     """16 scenes (grids 64^3..256^3, 2-20 % occupied, 64^2..1024^2 rays):
     one graph-captured batched pass vs 16 sequential single-scene calls."""
@@ -330,6 +349,7 @@ def main():
     if not args.no_side:
         line["composite"] = composite_side(api, torch, scenes, hdda, N, min(args.steps, 20))
         line["batched"] = batched_side(api, torch, scenes, min(args.steps, 10))
+        line["cascades"] = cascades_side(api, torch, scenes, min(args.steps, 10), 2)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_stride)
     print(json.dumps(line), flush=True)

@@ -128,7 +128,15 @@ ogv_status ogv_grid_to_dense(const ogv_grid *grid, uint8_t *occ_out_dev, void *s
 
 void ogv_grid_destroy(ogv_grid *grid);
 
-/* Workspace bytes a sample call needs for n_rays rays and this lattice. */
+/* Workspace bytes a sample call needs for n_rays rays and this lattice.
+ * With a growing step (OGV_STEP_CONE) the workspace also keeps the lattice's
+ * point table between calls, beside a header with near, far, cone, dt_min,
+ * the table's length and a 64-bit hash of its entries.  A call on the same
+ * workspace whose parameters match the header, and whose table still hashes
+ * to it, reuses the table; any other call rebuilds it (a sequential pass of
+ * about 50 ns per lattice point).  The caller may overwrite the workspace
+ * between calls (except between a count and its fill); it only costs the
+ * rebuild. */
 ogv_status ogv_sample_workspace_size(int64_t n_rays, float near_t, float far_t, const ogv_step *step_host,
                                      size_t *bytes_host);
 
@@ -194,9 +202,12 @@ ogv_status ogv_composite_fwd(const int64_t *offsets_dev, int64_t n_rays, const f
 /* Backward of ogv_composite_fwd: given g_rgb (float32 [n_rays][3]) and
  * g_opacity (float32 [n_rays], nullable = zero), writes
  * d_sigma_i = dt_i (g_rgb . (T_{i+1} c_i - sum_{k>i} w_k c_k) + g_opacity T_n)
- * and d_rgb_i = w_i g_rgb (float32 [S] and [S][3]). */
-ogv_status ogv_composite_bwd(const int64_t *offsets_dev, int64_t n_rays, const float *t0_dev, const float *t1_dev,
-                             const float *sigma_dev, const float *rgb_dev, const float *g_rgb_dev,
+ * and d_rgb_i = w_i g_rgb (float32 [S] and [S][3]), S = n_samples, the length
+ * of the sample arrays (>= offsets[n_rays]).  Samples no ray owns (before
+ * offsets[0] or from offsets[n_rays] on) get zero, so the outputs need no
+ * clearing beforehand. */
+ogv_status ogv_composite_bwd(const int64_t *offsets_dev, int64_t n_rays, int64_t n_samples, const float *t0_dev,
+                             const float *t1_dev, const float *sigma_dev, const float *rgb_dev, const float *g_rgb_dev,
                              const float *g_opacity_dev, float *d_sigma_dev, float *d_rgb_dev, void *stream);
 
 /* ---------------------------------------------------------------- batches

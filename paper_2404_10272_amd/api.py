@@ -73,7 +73,7 @@ SIGNATURES = {
     "ogv_sample_rays": (I32, [VP, ctypes.POINTER(_Opts), VP, VP, I64, F32, F32, ctypes.POINTER(_Step), VP, I64, VP, VP,
                               VP, VP, VP, VP, SZ, VP]),
     "ogv_composite_fwd": (I32, [VP, I64, VP, VP, VP, VP, VP, VP, VP]),
-    "ogv_composite_bwd": (I32, [VP, I64, VP, VP, VP, VP, VP, VP, VP, VP, VP]),
+    "ogv_composite_bwd": (I32, [VP, I64, I64, VP, VP, VP, VP, VP, VP, VP, VP, VP]),
     "ogv_batch_create": (I32, [ctypes.POINTER(_Scene), I32, I32, ctypes.POINTER(_Tune), ctypes.POINTER(VP), VP]),
     "ogv_batch_info_get": (I32, [VP, ctypes.POINTER(_BatchInfo), VP]),
     "ogv_batch_launch": (I32, [VP, VP, I64, VP, VP, VP, VP, VP]),
@@ -342,10 +342,10 @@ def composite_forward(offsets, t0, t1, sigma, rgb):
 
 
 def composite_backward(offsets, t0, t1, sigma, rgb, g_rgb, g_opacity):
-    d_sigma = torch.zeros_like(sigma)
-    d_rgb = torch.zeros_like(rgb)
+    d_sigma = torch.empty_like(sigma)   # every entry is written (zero where no ray owns it)
+    d_rgb = torch.empty_like(rgb)
     n = offsets.numel() - 1
-    _check(lib().ogv_composite_bwd(_ptr(offsets), n, _ptr(t0), _ptr(t1), _ptr(sigma), _ptr(rgb), _ptr(g_rgb),
+    _check(lib().ogv_composite_bwd(_ptr(offsets), n, sigma.numel(), _ptr(t0), _ptr(t1), _ptr(sigma), _ptr(rgb), _ptr(g_rgb),
                                    _ptr(g_opacity), _ptr(d_sigma), _ptr(d_rgb), _stream()))
     return d_sigma, d_rgb
 

@@ -13,6 +13,7 @@
 // row (a DPP row) handles one ray, 16 consecutive samples per chunk.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "internal.hpp"
@@ -117,7 +118,8 @@ __global__ void __launch_bounds__(kBlock) composite_fwd_kernel(const int64_t *__
 // suffix sum plus the carry of later chunks), and sum_{k>i} w_k c_k by a row
 // suffix sum plus the carry -- never as C minus a prefix.
 __global__ void __launch_bounds__(kBlock) composite_bwd_kernel(
-    const int64_t *__restrict__ offsets, int64_t n_rays, const float *__restrict__ t0, const float *__restrict__ t1,
+    const int64_t *__restrict__ offsets, int64_t n_rays, int64_t n_samples, const float *__restrict__ t0,
+    const float *__restrict__ t1,
     const float *__restrict__ sigma, const float *__restrict__ rgb, const float *__restrict__ g_rgb,
     const float *__restrict__ g_opacity, float *__restrict__ d_sigma, float *__restrict__ d_rgb) {
     const int l = threadIdx.x & (kRow - 1);
@@ -194,6 +196,16 @@ __global__ void __launch_bounds__(kBlock) composite_bwd_kernel(
         }
         if (g0 == a) break;
     }
+    // samples no ray owns (before offsets[0], from offsets[n_rays] on) get zero gradient
+    const int64_t lo = offsets[0], hi = offsets[n_rays];
+    const int64_t before = lo < n_samples ? lo : n_samples, after = hi < n_samples ? n_samples - hi : 0;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < before + after; k += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = k < before ? k : hi + (k - before);
+        d_sigma[i] = 0.f;
+        d_rgb[3 * i + 0] = 0.f;
+        d_rgb[3 * i + 1] = 0.f;
+        d_rgb[3 * i + 2] = 0.f;
+    }
 }
 
 }  // namespace
@@ -214,17 +226,20 @@ extern "C" ogv_status ogv_composite_fwd(const int64_t *offsets, int64_t n_rays, 
     return OGV_OK;
 }
 
-extern "C" ogv_status ogv_composite_bwd(const int64_t *offsets, int64_t n_rays, const float *t0, const float *t1,
+extern "C" ogv_status ogv_composite_bwd(const int64_t *offsets, int64_t n_rays, int64_t n_samples, const float *t0,
+                                        const float *t1,
                                         const float *sigma, const float *rgb, const float *g_rgb,
                                         const float *g_opacity, float *d_sigma, float *d_rgb, void *stream) {
     if (n_rays < 0) OGV_FAIL(OGV_ERR_INVALID, "n_rays < 0");
-    if (n_rays == 0) return OGV_OK;
+    if (n_samples < 0) OGV_FAIL(OGV_ERR_INVALID, "n_samples < 0");
+    if (n_rays == 0 && n_samples == 0) return OGV_OK;
     if (!offsets || !t0 || !t1 || !sigma || !rgb || !g_rgb || !d_sigma || !d_rgb)
         OGV_FAIL(OGV_ERR_INVALID, "null argument");
     hipStream_t s = (hipStream_t)stream;
-    const unsigned blocks = (unsigned)((n_rays + kRaysPerBlock - 1) / kRaysPerBlock);
-    composite_bwd_kernel<<<blocks, kBlock, 0, s>>>(offsets, n_rays, t0, t1, sigma, rgb, g_rgb, g_opacity, d_sigma,
-                                                   d_rgb);
+    // at least one block, so that an empty ray range still zeroes the samples
+    const unsigned blocks = (unsigned)std::max<int64_t>((n_rays + kRaysPerBlock - 1) / kRaysPerBlock, 1);
+    composite_bwd_kernel<<<blocks, kBlock, 0, s>>>(offsets, n_rays, n_samples, t0, t1, sigma, rgb, g_rgb, g_opacity,
+                                                   d_sigma, d_rgb);
     OGV_CHECK_LAUNCH();
     return OGV_OK;
 }

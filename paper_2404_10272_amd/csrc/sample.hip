@@ -147,31 +147,95 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kEx
     }
 }
 
-// Growing-step lattice, one thread: t_0 = near, t_{k+1} = fl(t_k +
-// max(fl(t_k*cone), dt_min)), stored up to and including the first value
-// past far.  n_tab = -1 if the capacity ran out first.
-__global__ void cone_table_kernel(float tmin, float tmax, float cone, float dt_min, float *tab, int32_t cap,
-                                  int32_t *n_tab) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    float t = tmin;
-    int32_t k = 0;
-    while (k < cap) {
-        tab[k++] = t;
-        if (t > tmax) break;
-        float grow = __fmul_rn(t, cone);
-        float step = grow > dt_min ? grow : dt_min;
-        t = __fadd_rn(t, step);
-    }
-    *n_tab = (k > 0 && tab[k - 1] > tmax) ? k : -1;
+// Growing-step lattice: t_0 = near, t_{k+1} = fl(t_k + max(fl(t_k*cone),
+// dt_min)), stored up to and including the first value past far, then padded
+// to the capacity with that value so binary searches over the whole capacity
+// stay on written entries.  n_tab = -1 if the capacity ran out first.
+//
+// The recurrence is sequential (one lane, about 50 ns a point), so the table
+// is kept in the workspace between calls: a header beside it holds the four
+// parameters, the capacity, the length and a 64-bit hash of every entry.  A
+// call whose parameters match a header whose hash matches the table as it
+// stands returns at once; anything else (a new workspace, other parameters,
+// an overwritten table) rebuilds it.
+struct TableHeader {
+    uint64_t magic;
+    float tmin, tmax, cone, dt_min;
+    int32_t cap, n_tab;
+    uint64_t hash;
+};
+constexpr uint64_t kTableMagic = 0x314e4f4356474f00ull;
+constexpr int kTableThreads = 256;
+
+// SplitMix64's output function (Steele, Lea and Flood, 2014) of (index, bits):
+// summed with wrapping over the entries, so the order of the sum is free.
+__device__ __forceinline__ uint64_t entry_mix(int32_t k, float v) {
+    uint64_t z = ((uint64_t)(uint32_t)k << 32 | (uint64_t)__float_as_uint(v)) + 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
 }
 
-// Pads the growing-step table past its true length with its last value
-// (> far), so binary searches over the whole capacity stay on written entries.
-__global__ void cone_pad_kernel(float *tab, int32_t cap, const int32_t *n_tab) {
-    int32_t n = *n_tab;
-    if (n <= 0) return;
-    float last = tab[n - 1];
-    for (int32_t k = n + blockIdx.x * blockDim.x + threadIdx.x; k < cap; k += gridDim.x * blockDim.x) tab[k] = last;
+__device__ uint64_t table_hash(const float *tab, int32_t cap, uint64_t *s_part) {
+    uint64_t h = 0;
+    for (int32_t k = threadIdx.x; k < cap; k += kTableThreads) h += entry_mix(k, tab[k]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) h += __shfl_xor(h, off, 64);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = h;
+    __syncthreads();
+    uint64_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kTableThreads / 64; ++w) t += s_part[w];
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ bool same_float(float a, float b) { return __float_as_uint(a) == __float_as_uint(b); }
+
+__global__ void __launch_bounds__(kTableThreads) cone_table_kernel(float tmin, float tmax, float cone, float dt_min,
+                                                                  float *tab, int32_t cap, int32_t *n_tab,
+                                                                  TableHeader *hdr) {
+    __shared__ uint64_t s_part[kTableThreads / 64];
+    __shared__ int32_t s_n;
+    const uint64_t h_now = table_hash(tab, cap, s_part);
+    if (threadIdx.x == 0) {
+        const TableHeader H = *hdr;
+        const bool same = H.magic == kTableMagic && same_float(H.tmin, tmin) && same_float(H.tmax, tmax) &&
+                          same_float(H.cone, cone) && same_float(H.dt_min, dt_min) && H.cap == cap &&
+                          H.n_tab > 0 && H.n_tab == *n_tab && H.hash == h_now;
+        s_n = same ? 0 : -2;
+        if (!same) {
+            hdr->magic = 0;   // invalid until rebuilt
+            float t = tmin;
+            int32_t k = 0;
+            while (k < cap) {
+                tab[k++] = t;
+                if (t > tmax) break;
+                float grow = __fmul_rn(t, cone);
+                float step = grow > dt_min ? grow : dt_min;
+                t = __fadd_rn(t, step);
+            }
+            s_n = (k > 0 && tab[k - 1] > tmax) ? k : -1;
+            *n_tab = s_n;
+        }
+    }
+    __syncthreads();
+    const int32_t n = s_n;
+    if (n == 0 || n == -1) return;   // reused, or the capacity ran out (left invalid)
+    const float last = tab[n - 1];
+    for (int32_t k = n + threadIdx.x; k < cap; k += kTableThreads) tab[k] = last;
+    __syncthreads();
+    const uint64_t h_new = table_hash(tab, cap, s_part);
+    if (threadIdx.x == 0) {
+        hdr->tmin = tmin;
+        hdr->tmax = tmax;
+        hdr->cone = cone;
+        hdr->dt_min = dt_min;
+        hdr->cap = cap;
+        hdr->n_tab = n;
+        hdr->hash = h_new;
+        hdr->magic = kTableMagic;
+    }
 }
 
 __global__ void zero_kernel(int64_t *p, int32_t *q) {
@@ -239,7 +303,7 @@ namespace {
 
 struct Plan {
     int64_t n_rays;
-    size_t off_counts, off_nruns, off_runs, off_next, off_chunks, off_cnext, off_lost, off_tiles, off_tab, off_ntab,
+    size_t off_counts, off_nruns, off_runs, off_next, off_chunks, off_cnext, off_lost, off_tiles, off_tab, off_ntab, off_thdr,
         total;
     int32_t pool_cap;
     int64_t n_tiles;
@@ -271,6 +335,7 @@ bool make_plan(int64_t n_rays, float near_t, float far_t, const ogv_step *step, 
     p->off_tiles = take(sizeof(int64_t) * (size_t)(p->n_tiles + 1));
     p->off_tab = take(sizeof(float) * (size_t)p->tab_cap);
     p->off_ntab = take(sizeof(int32_t) * 4);
+    p->off_thdr = take(sizeof(TableHeader));
     p->total = off;
     return true;
 }
@@ -392,9 +457,8 @@ ogv_status build_table(float near_t, float far_t, const ogv_step *step, void *ws
     if (step->kind != OGV_STEP_CONE || p.tab_cap == 0) return OGV_OK;
     float *tab = (float *)((char *)ws + p.off_tab);
     int32_t *n_tab = (int32_t *)((char *)ws + p.off_ntab);
-    cone_table_kernel<<<1, 64, 0, s>>>(near_t, far_t, step->cone, step->dt_min, tab, p.tab_cap, n_tab);
-    OGV_CHECK_LAUNCH();
-    cone_pad_kernel<<<8, 256, 0, s>>>(tab, p.tab_cap, n_tab);
+    TableHeader *hdr = (TableHeader *)((char *)ws + p.off_thdr);
+    cone_table_kernel<<<1, kTableThreads, 0, s>>>(near_t, far_t, step->cone, step->dt_min, tab, p.tab_cap, n_tab, hdr);
     OGV_CHECK_LAUNCH();
     return OGV_OK;
 }

@@ -107,3 +107,34 @@ def test_empty_rays_give_zero(packed):
     C, A = api.composite_forward(off, e, e, e, torch.zeros((1, 3), device="cuda"))
     torch.cuda.synchronize()
     assert C.abs().sum().item() == 0 and A.abs().sum().item() == 0
+
+
+def test_backward_zeroes_samples_no_ray_owns(packed):
+    """ogv_composite_bwd writes every entry of its outputs: the gradient of a
+    middle range of rays over the full sample arrays is the full call's inside
+    the range and exactly zero outside it, whatever the buffers held."""
+    out, sigma, rgb, _ = packed
+    off = out["offsets"]
+    N = off.numel() - 1
+    S = out["t0"].numel()
+    sig = torch.from_numpy(sigma).cuda()
+    col = torch.from_numpy(rgb).cuda()
+    g_rgb = torch.from_numpy(np.random.default_rng(4003).random((N, 3), np.float32)).cuda()
+    g_a = torch.ones(N, device="cuda")
+    full_s, full_c = api.composite_backward(off, out["t0"], out["t1"], sig, col, g_rgb, g_a)
+    r0, r1 = N // 3, 2 * N // 3
+    sub = off[r0:r1 + 1].contiguous()
+    d_s = torch.full((S,), float("nan"), device="cuda")
+    d_c = torch.full((S, 3), float("nan"), device="cuda")
+    g_sub, a_sub = g_rgb[r0:r1].contiguous(), g_a[r0:r1].contiguous()
+    api._check(api.lib().ogv_composite_bwd(api._ptr(sub), r1 - r0, S, api._ptr(out["t0"]), api._ptr(out["t1"]),
+                                           api._ptr(sig), api._ptr(col), api._ptr(g_sub), api._ptr(a_sub),
+                                           api._ptr(d_s), api._ptr(d_c), api._stream()))
+    torch.cuda.synchronize()
+    a, b = int(off[r0].item()), int(off[r1].item())
+    assert 0 < a < b < S
+    for got, ref in ((d_s, full_s), (d_c, full_c)):
+        got, ref = got.cpu().numpy(), ref.cpu().numpy()
+        assert not np.isnan(got).any()
+        np.testing.assert_array_equal(got[a:b], ref[a:b])
+        assert (got[:a] == 0).all() and (got[b:] == 0).all()

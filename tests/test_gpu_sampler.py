@@ -338,3 +338,51 @@ def test_offsets_of_many_rays_take_the_long_scan(small):
     np.testing.assert_array_equal(got, want)
     np.testing.assert_array_equal(sp.scan().cpu().numpy(), want)   # a repeated scan agrees
     del sp, o, d
+
+
+def test_growing_step_table_kept_between_calls():
+    """The growing-step table stays in the workspace between calls. It must be
+    reused only when near, far, cone and dt_min match and the table is intact:
+    a repeat call, an overwritten workspace and changed parameters on the same
+    workspace layout must all give the oracle's samples."""
+    rng = np.random.default_rng(4242)
+    R, L = 24, 2
+    boxes = np.asarray([[-2.0 ** l] * 3 + [2.0 ** l] * 3 for l in range(L)], np.float32)
+    occ = (rng.random((L, R, R, R)) < 0.2).astype(np.uint8)
+    o, d = scenes.random_rays(4000, rng, -3.0, 3.0)
+    scene = oracle.Scene(occ, boxes)
+    g = gpu_grid("vdb", occ, boxes, 1)
+    od, dd = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
+    near, far = 0.25, 7.0
+    step_a = oracle.make_step("cone", cone=1 / 16, dt_min=0.02)
+    sp = api.Sampler(g, len(o), near, far, api.make_step(step_a), "branch")
+
+    def check(far_, step, what):
+        sp.far, sp.step = float(far_), api.make_step(step)
+        offsets = sp.count(od, dd)
+        S = int(offsets[len(o)].item())
+        ids = torch.empty(S, dtype=torch.int32, device="cuda")
+        t0, t1 = torch.empty(S, device="cuda"), torch.empty(S, device="cuda")
+        sp.fill(od, dd, ids, t0, t1)
+        torch.cuda.synchronize()
+        ref = oracle.sample_rays(scene, o, d, near, far_, step, "dense_branch")
+        got = {"offsets": offsets.cpu().numpy(), "ray_ids": ids.cpu().numpy(), "t0": t0.cpu().numpy(),
+               "t1": t1.cpu().numpy()}
+        assert S > 0, what
+        print(what, S, flush=True)
+        assert_same(got, ref, what)
+
+    check(far, step_a, "first call")
+    check(far, step_a, "repeat call")
+    sp.ws.random_(0, 256)
+    check(far, step_a, "after the workspace was overwritten")
+    # other parameters with the same workspace layout (the same table capacity bucket)
+    changed = None
+    for cone in (1 / 15.5, 1 / 16.5, 1 / 15.9, 1 / 16.1):
+        step_b = oracle.make_step("cone", cone=cone, dt_min=0.02)
+        if api.workspace_bytes(len(o), near, far, api.make_step(step_b)) == sp.ws_bytes:
+            changed = step_b
+            break
+    assert changed is not None, "no nearby cone factor keeps the workspace layout"
+    check(far, changed, "changed cone on the same layout")
+    check(far, step_a, "back to the first parameters")
