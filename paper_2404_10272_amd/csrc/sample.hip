@@ -49,7 +49,7 @@ __device__ __forceinline__ void add_tile_sums(int64_t ray, int32_t n, int64_t *_
 // go to the pool's slots and chunks; tile_sums[k] gains the counts of rays
 // k*kScanTile .. (k+1)*kScanTile-1.
 template <bool kVdb, bool kSkip, bool kLds, bool kL1>
-__global__ void __launch_bounds__(kBlock) count_kernel(GridView g, const float *__restrict__ origins,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(!kVdb && kL1 ? 8 : 1))) count_kernel(GridView g, const float *__restrict__ origins,
                                                        const float *__restrict__ dirs, int64_t n_rays, Lattice lat,
                                                        int32_t *__restrict__ counts, int32_t *__restrict__ nruns,
                                                        RunPool pool, int image_width,
