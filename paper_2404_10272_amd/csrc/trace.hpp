@@ -135,35 +135,38 @@ struct VdbCursor {
     uint64_t word;
 
     // Size of the largest uniform cell holding voxel (v0, v1, v2) and its
-    // occupancy; for a voxel inside a leaf the leaf and word are cached.  The
-    // root and slot tables are read on every call and their answer selected,
-    // so the lookup holds one divergent region (the leaf-word load) rather
-    // than three nested ones.
+    // occupancy; for a voxel inside a leaf the leaf and word are cached.  A
+    // voxel in the cached leaf block (most voxel steps) needs only the word
+    // and bit; otherwise the root and slot tables are read and a leaf found
+    // there becomes the cached one.
     __device__ __forceinline__ int classify(bool &o) {
         const int blk = ((v0 >> 3) << 20) | ((v1 >> 3) << 10) | (v2 >> 3);
-        const bool hit = blk == lblk;
-        // one root cell per level (the common case) needs no index arithmetic
-        const int NR = t.NR;
-        const int ri = NR == 1 ? lev : ((lev * NR + (v0 >> sh)) * NR + (v1 >> sh)) * NR + (v2 >> sh);
-        const int node = t.root[ri];
-        const int lg = t.ilog2, m = t.S - 1;
-        const int s = (((v0 >> 3) & m) << (2 * lg)) | (((v1 >> 3) & m) << lg) | ((v2 >> 3) & m);
-        const int c = t.slot[(max(node, 0) << (3 * lg)) | s];   // node 0's slots exist in any tree
-        const bool root_tile = !hit && node < 0;
-        const bool slot_tile = !hit && node >= 0 && c < 0;
-        if (!hit && node >= 0 && c >= 0) {
-            lblk = blk;
-            lbase = c * 8;
-            wx = -1;
+        int D = 1;
+        if (blk != lblk) {
+            const int NR = t.NR;
+            const int ri = NR == 1 ? lev : ((lev * NR + (v0 >> sh)) * NR + (v1 >> sh)) * NR + (v2 >> sh);
+            const int node = t.root[ri];
+            const int lg = t.ilog2, m = t.S - 1;
+            const int s = (((v0 >> 3) & m) << (2 * lg)) | (((v1 >> 3) & m) << lg) | ((v2 >> 3) & m);
+            const int c = t.slot[(max(node, 0) << (3 * lg)) | s];
+            const bool root_tile = node < 0;
+            const bool slot_tile = !root_tile && c < 0;
+            if (!root_tile && !slot_tile) {
+                lblk = blk;
+                lbase = c * 8;
+                wx = -1;
+            } else {
+                o = root_tile ? node == -2 : c == -2;
+                return root_tile ? (8 << t.ilog2) : 8;
+            }
         }
-        const int D = root_tile ? (8 << t.ilog2) : (slot_tile ? 8 : 1);
-        if (D == 1 && (v0 & 7) != wx) {
+        if ((v0 & 7) != wx) {
             wx = v0 & 7;
             word = t.leaves[lbase + wx];
         }
         const int bit = ((v1 & 7) << 3) | (v2 & 7);
         const uint32_t half = bit < 32 ? (uint32_t)word : (uint32_t)(word >> 32);
-        o = D == 1 ? ((half >> (bit & 31)) & 1u) != 0 : (root_tile ? node == -2 : c == -2);
+        o = ((half >> (bit & 31)) & 1u) != 0;
         return D;
     }
 
