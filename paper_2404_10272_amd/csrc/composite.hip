@@ -55,9 +55,13 @@ __device__ __forceinline__ float row_lane(float x, int src) {
 
 // Samples of one row are loaded kGroup chunks of 16 at a time, all loads of a
 // group issued before any of its arithmetic, so that one memory latency
-// covers 64 samples instead of 16.
+// covers kGroup * 16 samples instead of 16.  The backward keeps the ray's last
+// group in registers between its two passes, so a larger group there means
+// more rays read their inputs once.
 constexpr int kGroup = 4;
 constexpr int kSpan = kGroup * kRow;
+constexpr int kGroupBwd = 8;
+constexpr int kSpanBwd = kGroupBwd * kRow;
 
 // One 16-lane row per ray, 16 consecutive samples per chunk (coalesced
 // loads); the optical depth before each sample is a row prefix sum plus the
@@ -126,11 +130,11 @@ __global__ void __launch_bounds__(kBlock) composite_bwd_kernel(
     const int64_t r = (int64_t)blockIdx.x * kRaysPerBlock + (threadIdx.x / kRow);
     const bool live = r < n_rays;
     const int64_t a = live ? offsets[r] : 0, b = live ? offsets[r + 1] : 0;
-    const int64_t last = b > a ? a + ((b - a - 1) / kSpan) * kSpan : a;   // first sample of the last group
-    float dt[kGroup], tau[kGroup], xr[kGroup], xg[kGroup], xb[kGroup];
+    const int64_t last = b > a ? a + ((b - a - 1) / kSpanBwd) * kSpanBwd : a;   // first sample of the last group
+    float dt[kGroupBwd], tau[kGroupBwd], xr[kGroupBwd], xg[kGroupBwd], xb[kGroupBwd];
     auto load_group = [&](int64_t g0) {
 #pragma unroll
-        for (int c = 0; c < kGroup; ++c) {
+        for (int c = 0; c < kGroupBwd; ++c) {
             const int64_t i = g0 + c * kRow + l;
             dt[c] = tau[c] = xr[c] = xg[c] = xb[c] = 0.f;
             if (i < b) {
@@ -144,19 +148,19 @@ __global__ void __launch_bounds__(kBlock) composite_bwd_kernel(
     };
 
     float part = 0.f;
-    for (int64_t g0 = a; g0 < last; g0 += kSpan) {   // whole groups before the last
-        float q[kGroup];
+    for (int64_t g0 = a; g0 < last; g0 += kSpanBwd) {   // whole groups before the last
+        float q[kGroupBwd];
 #pragma unroll
-        for (int c = 0; c < kGroup; ++c) {
+        for (int c = 0; c < kGroupBwd; ++c) {
             const int64_t i = g0 + c * kRow + l;
             q[c] = sigma[i] * (t1[i] - t0[i]);
         }
 #pragma unroll
-        for (int c = 0; c < kGroup; ++c) part += q[c];
+        for (int c = 0; c < kGroupBwd; ++c) part += q[c];
     }
     load_group(last);
 #pragma unroll
-    for (int c = 0; c < kGroup; ++c) part += tau[c];
+    for (int c = 0; c < kGroupBwd; ++c) part += tau[c];
     const float total = row_lane(row_prefix(part), kRow - 1);
 
     const float gr = live ? g_rgb[3 * r + 0] : 0.f, gg = live ? g_rgb[3 * r + 1] : 0.f;
@@ -165,10 +169,10 @@ __global__ void __launch_bounds__(kBlock) composite_bwd_kernel(
     const float T_end = expf(-total);
     float after_tau = 0.f;                      // depth of the later chunks
     float ar = 0.f, ag = 0.f, ab = 0.f;         // sum of w c over the later chunks
-    for (int64_t g0 = last; g0 >= a; g0 -= kSpan) {   // row-uniform
+    for (int64_t g0 = last; g0 >= a; g0 -= kSpanBwd) {   // row-uniform
         if (g0 != last) load_group(g0);
 #pragma unroll
-        for (int c = kGroup - 1; c >= 0; --c) {
+        for (int c = kGroupBwd - 1; c >= 0; --c) {
             if (g0 + c * kRow >= b) continue;   // row-uniform
             const int64_t i = g0 + c * kRow + l;
             const bool ok = i < b;
