@@ -158,6 +158,28 @@ def cascades_side(api, torch, scenes, steps, warmup):
     return out
 
 
+def render_side(api, torch, scenes, hdda, w, steps):
+    """End-to-end frame on the 800x800 object workload: the sampler's step
+    (count + scan + fill) then one fused pass that evaluates a 12-blob
+    Gaussian field at every sample's midpoint and composites each ray.  The
+    field stands in for a trained one (random parameters, no weights)."""
+    blobs = scenes.blob_field()
+    field = api.blob_field(*blobs)
+    off = hdda.sp.offsets
+    render = lambda: api.render_blobs(off, hdda.o, hdda.d, hdda.t0, hdda.t1, field)
+    r_ms = time_events(torch, render, steps, 2)
+
+    def frame():
+        hdda.step()
+        render()
+
+    f_ms = time_events(torch, frame, steps, 2)
+    S, N, K = hdda.S, w.n_rays, len(blobs[1])
+    return {"blobs": K, "render_ms": r_ms, "frame_ms": f_ms, "frames_per_s": 1e3 / f_ms,
+            "render_GBps": (8 * S + 24 * N + 8 * (N + 1) + 16 * N) / (r_ms * 1e-3) / 1e9,
+            "samples": S}
+
+
 def batched_side(api, torch, scenes, steps):
     """16 scenes (grids 64^3..256^3, 2-20 % occupied, 64^2..1024^2 rays):
     one graph-captured batched pass vs 16 sequential single-scene calls."""
@@ -350,6 +372,7 @@ def main():
         line["composite"] = composite_side(api, torch, scenes, hdda, N, min(args.steps, 20))
         line["batched"] = batched_side(api, torch, scenes, min(args.steps, 10))
         line["cascades"] = cascades_side(api, torch, scenes, min(args.steps, 10), 2)
+        line["render"] = render_side(api, torch, scenes, hdda, w, min(args.steps, 20))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_stride)
     print(json.dumps(line), flush=True)

@@ -210,6 +210,34 @@ ogv_status ogv_composite_bwd(const int64_t *offsets_dev, int64_t n_rays, int64_t
                              const float *t1_dev, const float *sigma_dev, const float *rgb_dev, const float *g_rgb_dev,
                              const float *g_opacity_dev, float *d_sigma_dev, float *d_rgb_dev, void *stream);
 
+/* A synthetic radiance field: K Gaussian blobs (1 <= K <= OGV_MAX_BLOBS).
+ * At a point x, g_k = exp(-|x - centre_k|^2 / (2 radius_k^2)),
+ * sigma(x) = sum_k density_k g_k and colour(x) = sum_k density_k g_k
+ * colour_k / sigma(x) (0 where sigma is 0).  It stands in for the trained
+ * field that the sampler's points are fed to (Sec. 1); the paper's networks
+ * and weights are not part of this library. */
+#define OGV_MAX_BLOBS 16
+typedef struct {
+    int32_t n;
+    float centre[OGV_MAX_BLOBS][3];
+    float radius[OGV_MAX_BLOBS];   /* > 0 */
+    float density[OGV_MAX_BLOBS];  /* >= 0 */
+    float colour[OGV_MAX_BLOBS][3];
+} ogv_blob_field;
+
+/* Renders packed samples through a blob field in one pass: each sample's
+ * field value is taken at its interval midpoint o + d (t0 + t1) / 2 and
+ * composited as in ogv_composite_fwd (density and colour are never stored).
+ *   offsets_dev int64 [n_rays+1]; origins_dev, dirs_dev float32 [n_rays][3];
+ *   t0_dev, t1_dev float32 [S]; field_host read during the call only.
+ *   out_rgb_dev float32 [n_rays][3], out_opacity_dev float32 [n_rays]
+ *   (nullable).  Errors: OGV_ERR_INVALID on null pointers, n_rays < 0, a
+ *   blob count outside 1..OGV_MAX_BLOBS, a radius <= 0 or a density < 0. */
+ogv_status ogv_render_blobs(const int64_t *offsets_dev, int64_t n_rays, const float *origins_dev,
+                            const float *dirs_dev, const float *t0_dev, const float *t1_dev,
+                            const ogv_blob_field *field_host, float *out_rgb_dev, float *out_opacity_dev,
+                            void *stream);
+
 /* ---------------------------------------------------------------- batches
  * Many scenes, uneven grids and ray counts, in one graph-captured pass: a
  * persistent counting kernel pulls chunks of rays from a queue that spans

@@ -17,6 +17,7 @@ import os
 import numpy as np
 
 from .composite import composite_forward, composite_backward, composite_loss_grad  # noqa: F401
+from .render import blob_field, render_blobs  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libogoracle.so")

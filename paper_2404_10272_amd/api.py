@@ -52,6 +52,15 @@ class _BatchInfo(ctypes.Structure):
                 ("tune_ms", ctypes.c_float)]
 
 
+MAX_BLOBS = 16
+
+
+class _BlobField(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("centre", (ctypes.c_float * 3) * MAX_BLOBS),
+                ("radius", ctypes.c_float * MAX_BLOBS), ("density", ctypes.c_float * MAX_BLOBS),
+                ("colour", (ctypes.c_float * 3) * MAX_BLOBS)]
+
+
 _lib = None
 VP, I32, I64, F32, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
 
@@ -74,6 +83,7 @@ SIGNATURES = {
                               VP, VP, VP, VP, SZ, VP]),
     "ogv_composite_fwd": (I32, [VP, I64, VP, VP, VP, VP, VP, VP, VP]),
     "ogv_composite_bwd": (I32, [VP, I64, I64, VP, VP, VP, VP, VP, VP, VP, VP, VP]),
+    "ogv_render_blobs": (I32, [VP, I64, VP, VP, VP, VP, ctypes.POINTER(_BlobField), VP, VP, VP]),
     "ogv_batch_create": (I32, [ctypes.POINTER(_Scene), I32, I32, ctypes.POINTER(_Tune), ctypes.POINTER(VP), VP]),
     "ogv_batch_info_get": (I32, [VP, ctypes.POINTER(_BatchInfo), VP]),
     "ogv_batch_launch": (I32, [VP, VP, I64, VP, VP, VP, VP, VP]),
@@ -348,6 +358,34 @@ def composite_backward(offsets, t0, t1, sigma, rgb, g_rgb, g_opacity):
     _check(lib().ogv_composite_bwd(_ptr(offsets), n, sigma.numel(), _ptr(t0), _ptr(t1), _ptr(sigma), _ptr(rgb), _ptr(g_rgb),
                                    _ptr(g_opacity), _ptr(d_sigma), _ptr(d_rgb), _stream()))
     return d_sigma, d_rgb
+
+
+def blob_field(centres, radii, densities, colours):
+    """The C struct of a Gaussian-blob field from K centres [K,3], radii [K],
+    densities [K] and colours [K,3] (1 <= K <= 16)."""
+    import numpy as np
+    c = np.asarray(centres, np.float32).reshape(-1, 3)
+    k = c.shape[0]
+    f = _BlobField()
+    f.n = k
+    for i in range(min(k, MAX_BLOBS)):
+        for q in range(3):
+            f.centre[i][q] = float(c[i, q])
+            f.colour[i][q] = float(np.asarray(colours, np.float32).reshape(-1, 3)[i, q])
+        f.radius[i] = float(np.asarray(radii, np.float32)[i])
+        f.density[i] = float(np.asarray(densities, np.float32)[i])
+    return f
+
+
+def render_blobs(offsets, origins, dirs, t0, t1, field):
+    """Pixel (rgb[N,3], opacity[N]) of packed samples rendered through a blob
+    field (each sample at its interval midpoint), one fused pass."""
+    o, d, n = _rays(origins, dirs)
+    out_rgb = torch.empty((n, 3), dtype=torch.float32, device=o.device)
+    out_a = torch.empty(n, dtype=torch.float32, device=o.device)
+    _check(lib().ogv_render_blobs(_ptr(offsets), n, _ptr(o), _ptr(d), _ptr(t0), _ptr(t1), ctypes.byref(field),
+                                  _ptr(out_rgb), _ptr(out_a), _stream()))
+    return out_rgb, out_a
 
 
 class Composite(torch.autograd.Function):

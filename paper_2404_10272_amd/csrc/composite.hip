@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 
 #include "internal.hpp"
@@ -212,6 +213,92 @@ __global__ void __launch_bounds__(kBlock) composite_bwd_kernel(
     }
 }
 
+// ------------------------------------------------------------------ blob field
+
+// Blob parameters as the kernel takes them (a by-value argument, so they sit
+// in scalar registers): nk = -log2(e) / (2 radius^2), so that
+// g = exp2(|x - c|^2 nk) is one hardware exp2.
+struct BlobArgs {
+    int n;
+    float cx[OGV_MAX_BLOBS], cy[OGV_MAX_BLOBS], cz[OGV_MAX_BLOBS], nk[OGV_MAX_BLOBS];
+    float a[OGV_MAX_BLOBS], r[OGV_MAX_BLOBS], g[OGV_MAX_BLOBS], b[OGV_MAX_BLOBS];
+};
+
+// One 16-lane row per ray, the composite forward's structure, with sigma and
+// colour computed in registers from the field at each sample's midpoint
+// instead of being read.
+__global__ void __launch_bounds__(kBlock) render_blobs_kernel(const int64_t *__restrict__ offsets, int64_t n_rays,
+                                                             const float *__restrict__ origins,
+                                                             const float *__restrict__ dirs,
+                                                             const float *__restrict__ t0,
+                                                             const float *__restrict__ t1, BlobArgs f,
+                                                             float *__restrict__ out_rgb,
+                                                             float *__restrict__ out_opacity) {
+    const int l = threadIdx.x & (kRow - 1);
+    const int64_t r = (int64_t)blockIdx.x * kRaysPerBlock + (threadIdx.x / kRow);
+    const bool live = r < n_rays;
+    const int64_t a = live ? offsets[r] : 0, b = live ? offsets[r + 1] : 0;
+    float o[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 0.f};
+    if (live && b > a) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            o[q] = origins[3 * r + q];
+            d[q] = dirs[3 * r + q];
+        }
+    }
+    float cr = 0.f, cg = 0.f, cb = 0.f, acc = 0.f, carry = 0.f;
+    for (int64_t g0 = a; g0 < b; g0 += kSpan) {   // row-uniform
+        float mid[kGroup], dt[kGroup];
+#pragma unroll
+        for (int c = 0; c < kGroup; ++c) {
+            const int64_t i = g0 + c * kRow + l;
+            mid[c] = dt[c] = 0.f;
+            if (i < b) {
+                const float u = t0[i], v = t1[i];
+                mid[c] = 0.5f * (u + v);
+                dt[c] = v - u;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kGroup; ++c) {
+            if (g0 + c * kRow >= b) break;   // row-uniform
+            const bool ok = g0 + c * kRow + l < b;
+            const float x = fmaf(d[0], mid[c], o[0]), y = fmaf(d[1], mid[c], o[1]), z = fmaf(d[2], mid[c], o[2]);
+            float sig = 0.f, nr = 0.f, ng = 0.f, nb = 0.f;
+            for (int k = 0; k < f.n; ++k) {
+                const float ex = x - f.cx[k], ey = y - f.cy[k], ez = z - f.cz[k];
+                const float d2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+                const float w = f.a[k] * __builtin_amdgcn_exp2f(d2 * f.nk[k]);
+                sig += w;
+                nr = fmaf(w, f.r[k], nr);
+                ng = fmaf(w, f.g[k], ng);
+                nb = fmaf(w, f.b[k], nb);
+            }
+            const float inv = sig > 0.f ? 1.0f / sig : 0.f;
+            const float tau = ok ? sig * dt[c] : 0.f;
+            const float incl = row_prefix(tau);
+            const float T = expf(-(carry + incl - tau));
+            const float w = ok ? T * (-expm1f(-tau)) : 0.f;
+            const float wi = w * inv;
+            cr = fmaf(wi, nr, cr);
+            cg = fmaf(wi, ng, cg);
+            cb = fmaf(wi, nb, cb);
+            acc += w;
+            carry += row_lane(incl, kRow - 1);
+        }
+    }
+    cr = row_prefix(cr);
+    cg = row_prefix(cg);
+    cb = row_prefix(cb);
+    acc = row_prefix(acc);
+    if (live && l == kRow - 1) {
+        out_rgb[3 * r + 0] = cr;
+        out_rgb[3 * r + 1] = cg;
+        out_rgb[3 * r + 2] = cb;
+        if (out_opacity) out_opacity[r] = acc;
+    }
+}
+
 }  // namespace
 }  // namespace ogv
 
@@ -244,6 +331,36 @@ extern "C" ogv_status ogv_composite_bwd(const int64_t *offsets, int64_t n_rays, 
     const unsigned blocks = (unsigned)std::max<int64_t>((n_rays + kRaysPerBlock - 1) / kRaysPerBlock, 1);
     composite_bwd_kernel<<<blocks, kBlock, 0, s>>>(offsets, n_rays, n_samples, t0, t1, sigma, rgb, g_rgb, g_opacity,
                                                    d_sigma, d_rgb);
+    OGV_CHECK_LAUNCH();
+    return OGV_OK;
+}
+
+extern "C" ogv_status ogv_render_blobs(const int64_t *offsets, int64_t n_rays, const float *origins, const float *dirs,
+                                       const float *t0, const float *t1, const ogv_blob_field *field, float *out_rgb,
+                                       float *out_opacity, void *stream) {
+    if (n_rays < 0) OGV_FAIL(OGV_ERR_INVALID, "n_rays < 0");
+    if (!field) OGV_FAIL(OGV_ERR_INVALID, "null field");
+    if (field->n < 1 || field->n > OGV_MAX_BLOBS) OGV_FAIL(OGV_ERR_INVALID, "blob count outside 1..16");
+    BlobArgs f{};
+    f.n = field->n;
+    for (int k = 0; k < field->n; ++k) {
+        const float rad = field->radius[k], den = field->density[k];
+        if (!(rad > 0.f) || !(den >= 0.f) || !std::isfinite(rad) || !std::isfinite(den))
+            OGV_FAIL(OGV_ERR_INVALID, "blob radius must be > 0 and density >= 0, both finite");
+        f.cx[k] = field->centre[k][0];
+        f.cy[k] = field->centre[k][1];
+        f.cz[k] = field->centre[k][2];
+        f.nk[k] = (float)(-1.4426950408889634 / (2.0 * (double)rad * (double)rad));   // -log2(e) / (2 r^2)
+        f.a[k] = den;
+        f.r[k] = field->colour[k][0];
+        f.g[k] = field->colour[k][1];
+        f.b[k] = field->colour[k][2];
+    }
+    if (n_rays == 0) return OGV_OK;
+    if (!offsets || !origins || !dirs || !t0 || !t1 || !out_rgb) OGV_FAIL(OGV_ERR_INVALID, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    const unsigned blocks = (unsigned)((n_rays + kRaysPerBlock - 1) / kRaysPerBlock);
+    render_blobs_kernel<<<blocks, kBlock, 0, s>>>(offsets, n_rays, origins, dirs, t0, t1, f, out_rgb, out_opacity);
     OGV_CHECK_LAUNCH();
     return OGV_OK;
 }

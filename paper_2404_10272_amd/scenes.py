@@ -32,7 +32,7 @@ import math
 
 import numpy as np
 
-SEED_BASE = {"small": 1000, "object": 2000, "unbounded": 3000, "composite": 4000, "batched": 5000}
+SEED_BASE = {"small": 1000, "object": 2000, "unbounded": 3000, "composite": 4000, "batched": 5000, "render": 6000}
 
 
 @dataclass
@@ -288,6 +288,19 @@ def composite_inputs(n_samples, n_rays, seed=SEED_BASE["composite"]):
     rgb = rng.random((n_samples, 3)).astype(np.float32)
     target = rng.random((n_rays, 3)).astype(np.float32)
     return sigma, rgb, target
+
+
+def blob_field(n_blobs=12, seed=SEED_BASE["render"]):
+    """A synthetic radiance field standing in for a trained one: Gaussian blobs
+    with centres ~ U(-0.7, 0.7)^3 (where the object scene's shells sit), radii
+    ~ U(0.2, 0.5), densities ~ U(5, 40) and colours ~ U[0,1]^3.  Returns
+    float32 arrays (centres [K,3], radii [K], densities [K], colours [K,3])."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(-0.7, 0.7, size=(n_blobs, 3)).astype(np.float32)
+    radii = rng.uniform(0.2, 0.5, size=n_blobs).astype(np.float32)
+    dens = rng.uniform(5.0, 40.0, size=n_blobs).astype(np.float32)
+    cols = rng.random((n_blobs, 3)).astype(np.float32)
+    return centres, radii, dens, cols
 
 
 def workload(name, **kw):

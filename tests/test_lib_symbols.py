@@ -70,3 +70,16 @@ def test_scan_entry_validates_on_host():
     assert L.ogv_sample_scan(1000, fake, None, n.value, None) == -2
     assert L.ogv_sample_scan(1000, fake, fake, 64, None) == -2
     assert b"workspace" in L.ogv_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_render_blobs_validates_the_field_on_host():
+    from paper_2404_10272_amd import api
+    lib = api.lib()
+    good = api.blob_field([[0, 0, 0]], [0.5], [1.0], [[1, 1, 1]])
+    assert lib.ogv_render_blobs(None, 0, None, None, None, None, ctypes.byref(good), None, None, None) == 0
+    for centres, radii, dens in [([], [], []), ([[0, 0, 0]], [0.0], [1.0]), ([[0, 0, 0]], [0.5], [-1.0]),
+                                 ([[0, 0, 0]] * 17, [0.5] * 17, [1.0] * 17)]:
+        f = api.blob_field(centres, radii, dens, [[1, 1, 1]] * len(centres))
+        assert lib.ogv_render_blobs(None, 0, None, None, None, None, ctypes.byref(f), None, None, None) == -1
+    assert lib.ogv_render_blobs(None, 0, None, None, None, None, None, None, None, None) == -1
