@@ -285,6 +285,8 @@ def main():
     W = w.image[0]
     hdda = Timed(api, torch, vdb, w, o, d, args.variant, W)
     ms, walk_ms, scan_ms, fill_ms = hdda.run(args.steps, args.warmup)
+    # in-place asynchronous refresh of the tree (same occupancy, so the grid is unchanged)
+    refresh_ms = time_events(torch, lambda: vdb.refresh(occ), 10, 2)
     compare = {}
     if not args.primary_only:
         # the other loop variant, row-major lanes, and the dense-grid march
@@ -357,7 +359,7 @@ def main():
         "samples_per_s": S / (ms * 1e-3),
         "vdb": {"ms_per_step": ms, "count_scan_ms": count_ms, "walk_ms": walk_ms, "scan_ms": scan_ms,
                 "fill_ms": fill_ms, "rays_per_s": N / (ms * 1e-3),
-                "bytes": G, "leaves": vinfo["n_leaves"], "build_ms": build_ms},
+                "bytes": G, "leaves": vinfo["n_leaves"], "build_ms": build_ms, "refresh_ms": refresh_ms},
         "step_bytes": step_bytes,
         "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "runs": runs,

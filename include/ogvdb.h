@@ -128,6 +128,20 @@ ogv_status ogv_grid_to_dense(const ogv_grid *grid, uint8_t *occ_out_dev, void *s
 
 void ogv_grid_destroy(ogv_grid *grid);
 
+/* Re-derives a grid from a new occupancy occ_dev of the same shape (levels,
+ * resolution, boxes and, for a VDB, internal node size are kept), in place
+ * and asynchronously on the stream: no allocation and no host
+ * synchronization, so a training loop can refresh its grid every few steps
+ * (the paper's GPU tree is read-only and left this as future work, Sec. 5).
+ * A VDB is rebuilt by the build's own kernels into the storage it was given
+ * for the worst case, re-classifying every 8^3 block (R^3 bytes read); the
+ * build's scratch stays with the grid for this.  Sampling calls on the same
+ * stream see the new grid; calls on other streams must be ordered by the
+ * caller, and no other call may use the grid while a refresh runs.  After a
+ * refresh, ogv_grid_info_get waits for this stream.  OGV_ERR_INVALID on null
+ * arguments. */
+ogv_status ogv_grid_refresh(ogv_grid *grid, const uint8_t *occ_dev, void *stream);
+
 /* Workspace bytes a sample call needs for n_rays rays and this lattice.
  * With a growing step (OGV_STEP_CONE) the workspace also keeps the lattice's
  * point table between calls, beside a header with near, far, cone, dt_min,

@@ -71,6 +71,7 @@ SIGNATURES = {
     "ogv_grid_info_get": (I32, [VP, ctypes.POINTER(_Info)]),
     "ogv_grid_to_dense": (I32, [VP, VP, VP]),
     "ogv_grid_destroy": (None, [VP]),
+    "ogv_grid_refresh": (I32, [VP, VP, VP]),
     "ogv_sample_workspace_size": (I32, [I64, F32, F32, ctypes.POINTER(_Step), ctypes.POINTER(SZ)]),
     "ogv_sample_count": (I32, [VP, ctypes.POINTER(_Opts), VP, VP, I64, F32, F32, ctypes.POINTER(_Step), VP, VP, SZ,
                                VP]),
@@ -138,10 +139,12 @@ def _variant(v):
 class Grid:
     """A built grid on the current device: dense bitfield (plain method) or VDB tree."""
 
-    def __init__(self, handle, kind, boxes):
+    def __init__(self, handle, kind, boxes, shape=None):
         self._h = handle
         self.kind = kind
         self.boxes = boxes
+        self.shape = shape          # (L, R, R, R) of the occupancy it was built from
+        self._occ_in_use = None     # occupancy a refresh may still be reading
 
     @property
     def handle(self):
@@ -157,6 +160,19 @@ class Grid:
         out = torch.empty((i["n_levels"],) + (i["res"],) * 3, dtype=torch.uint8, device="cuda")
         _check(lib().ogv_grid_to_dense(self._h, _ptr(out), _stream()))
         return out
+
+    def refresh(self, occ, stream=None):
+        """Re-derives this grid from a new occupancy of the same shape, in
+        place and asynchronously (no allocation, no host synchronization)."""
+        if occ.dim() == 3:
+            occ = occ.unsqueeze(0)
+        if not occ.is_cuda:
+            raise OgvError("occupancy must be a device tensor")
+        occ = occ.to(torch.uint8).contiguous()
+        if self.shape is not None and tuple(occ.shape) != tuple(self.shape):
+            raise OgvError(f"occupancy shape {tuple(occ.shape)} differs from the grid's {tuple(self.shape)}")
+        _check(lib().ogv_grid_refresh(self._h, _ptr(occ), _stream(stream)))
+        self._occ_in_use = occ
 
     def close(self):
         if self._h:
@@ -187,14 +203,14 @@ def build_dense(occ, boxes, stream=None):
     occ, L, R, b = _grid_args(occ, boxes)
     h = ctypes.c_void_p()
     _check(lib().ogv_dense_build(L, R, b, _ptr(occ), ctypes.byref(h), _stream(stream)))
-    return Grid(h, "dense", boxes)
+    return Grid(h, "dense", boxes, tuple(occ.shape))
 
 
 def build_vdb(occ, boxes, internal_log2=4, stream=None):
     occ, L, R, b = _grid_args(occ, boxes)
     h = ctypes.c_void_p()
     _check(lib().ogv_vdb_build(L, R, b, _ptr(occ), int(internal_log2), ctypes.byref(h), _stream(stream)))
-    return Grid(h, "vdb", boxes)
+    return Grid(h, "vdb", boxes, tuple(occ.shape))
 
 
 def workspace_bytes(n_rays, near, far, step):

@@ -287,6 +287,52 @@ ogv_status check_common(int32_t L, int32_t R, const float *boxes, const uint8_t 
     return OGV_OK;
 }
 
+// Scratch of a VDB build, kept with the grid so that a refresh can run the
+// same kernels again without allocating.
+struct VdbBuildState {
+    BuildDims b;
+    void *scratch = nullptr;
+    int32_t *kind, *mixed, *root_kind, *is_node;
+    uint64_t *masks;
+    int64_t *leaf_idx, *node_idx, *tiles;
+};
+
+// Classifies every 8^3 block of occ and writes the tree into the grid's
+// storage (sized for the worst case at build time): the kernels of a build,
+// all asynchronous on s.
+hipError_t enqueue_vdb(ogv_grid *g, const VdbBuildState &st, const uint8_t *occ, hipStream_t s) {
+    const BuildDims &b = st.b;
+    GridView &v = g->view;
+    zero_counts_kernel<<<1, 64, 0, s>>>(g->counts_dev);
+    classify_kernel<<<(unsigned)((b.n_block + 3) / 4), 256, 0, s>>>(b, occ, st.kind, st.mixed, st.masks);
+    root_kernel<<<(unsigned)b.n_root, 256, 0, s>>>(b, st.kind, st.root_kind, st.is_node);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_excl_scan(st.is_node, b.n_root, st.node_idx, st.tiles, 0, nullptr, s);
+    if (e == hipSuccess) {
+        root_write_kernel<<<(unsigned)((b.n_root + 255) / 256), 256, 0, s>>>(b, st.root_kind, st.node_idx,
+                                                                            (int32_t *)v.root, g->counts_dev);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = launch_excl_scan(st.mixed, b.n_block, st.leaf_idx, st.tiles, 0, nullptr, s);
+    if (e == hipSuccess) {
+        node_write_kernel<<<(unsigned)((b.n_root * b.W + 3) / 4), 256, 0, s>>>(
+            b, st.root_kind, st.node_idx, st.kind, st.leaf_idx, (uint64_t *)v.child, (uint64_t *)v.value,
+            (uint32_t *)v.rank, (int32_t *)v.slot, g->counts_dev);
+        leaf_write_kernel<<<(unsigned)((b.n_block * 8 + 255) / 256), 256, 0, s>>>(b, st.mixed, st.leaf_idx, st.masks,
+                                                                                 (uint64_t *)v.leaves, g->counts_dev);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+void free_state(ogv_grid *g) {
+    if (!g->state) return;
+    VdbBuildState *st = (VdbBuildState *)g->state;
+    (void)hipFree(st->scratch);
+    delete st;
+    g->state = nullptr;
+}
+
 }  // namespace
 }  // namespace ogv
 
@@ -399,6 +445,10 @@ extern "C" ogv_status ogv_vdb_build(int32_t L, int32_t R, const float *boxes, co
         delete g;
         OGV_FAIL(OGV_ERR_OOM, "device allocation of " + std::to_string(scratch_total) + " bytes failed");
     }
+    VdbBuildState *bs = new VdbBuildState();
+    bs->b = b;
+    bs->scratch = scratch;
+    g->state = bs;
     g->mem_bytes = total;
     std::memcpy(g->boxes_host, boxes, sizeof(float) * 6 * L);
     g->build_stream = s;
@@ -422,40 +472,26 @@ extern "C" ogv_status ogv_vdb_build(int32_t L, int32_t R, const float *boxes, co
     v.leaves = (const uint64_t *)(m + o_leaves);
     g->counts_dev = (VdbCounts *)(m + o_counts);
 
-    int32_t *kind = (int32_t *)(t + t_kind), *mixed = (int32_t *)(t + t_mixed);
-    uint64_t *masks = (uint64_t *)(t + t_masks);
-    int64_t *leaf_idx = (int64_t *)(t + t_leafidx), *node_idx = (int64_t *)(t + t_nodeidx);
-    int32_t *root_kind = (int32_t *)(t + t_rootkind), *is_node = (int32_t *)(t + t_isnode);
-    int64_t *tiles = (int64_t *)(t + t_tiles);
+    bs->kind = (int32_t *)(t + t_kind);
+    bs->mixed = (int32_t *)(t + t_mixed);
+    bs->masks = (uint64_t *)(t + t_masks);
+    bs->leaf_idx = (int64_t *)(t + t_leafidx);
+    bs->node_idx = (int64_t *)(t + t_nodeidx);
+    bs->root_kind = (int32_t *)(t + t_rootkind);
+    bs->is_node = (int32_t *)(t + t_isnode);
+    bs->tiles = (int64_t *)(t + t_tiles);
 
     hipError_t e = hipMemcpyAsync((void *)v.boxes, g->boxes_host, sizeof(float) * 6 * L, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
-        zero_counts_kernel<<<1, 64, 0, s>>>(g->counts_dev);
         geom_kernel<<<1, 64, 0, s>>>(v.boxes, L, R, (float *)v.geom);
-        classify_kernel<<<(unsigned)((b.n_block + 3) / 4), 256, 0, s>>>(b, occ, kind, mixed, masks);
-        root_kernel<<<(unsigned)b.n_root, 256, 0, s>>>(b, kind, root_kind, is_node);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = launch_excl_scan(is_node, b.n_root, node_idx, tiles, 0, nullptr, s);
-    if (e == hipSuccess) {
-        root_write_kernel<<<(unsigned)((b.n_root + 255) / 256), 256, 0, s>>>(b, root_kind, node_idx,
-                                                                            (int32_t *)v.root, g->counts_dev);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = launch_excl_scan(mixed, b.n_block, leaf_idx, tiles, 0, nullptr, s);
-    if (e == hipSuccess) {
-        node_write_kernel<<<(unsigned)((b.n_root * b.W + 3) / 4), 256, 0, s>>>(
-            b, root_kind, node_idx, kind, leaf_idx, (uint64_t *)v.child, (uint64_t *)v.value, (uint32_t *)v.rank,
-            (int32_t *)v.slot, g->counts_dev);
-        leaf_write_kernel<<<(unsigned)((b.n_block * 8 + 255) / 256), 256, 0, s>>>(b, mixed, leaf_idx, masks,
-                                                                                 (uint64_t *)v.leaves, g->counts_dev);
-        e = hipGetLastError();
-    }
-    // scratch is released once the build has run; this also keeps the host
-    // copy of the boxes alive long enough for the async copy
+    if (e == hipSuccess) e = enqueue_vdb(g, *bs, occ, s);
+    // the host copy of the boxes must outlive the async copy; the build
+    // scratch stays with the grid for refreshes
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(scratch);
     if (e != hipSuccess) {
+        free_state(g);
         (void)hipFree(g->mem);
         delete g;
         OGV_FAIL(OGV_ERR_HIP, std::string("VDB build failed: ") + hipGetErrorString(e));
@@ -510,6 +546,26 @@ extern "C" ogv_status ogv_grid_to_dense(const ogv_grid *grid, uint8_t *out, void
 
 extern "C" void ogv_grid_destroy(ogv_grid *grid) {
     if (!grid) return;
+    free_state(grid);
     (void)hipFree(grid->mem);
     delete grid;
+}
+
+extern "C" ogv_status ogv_grid_refresh(ogv_grid *grid, const uint8_t *occ, void *stream) {
+    if (!grid || !occ) OGV_FAIL(OGV_ERR_INVALID, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    GridView &v = grid->view;
+    if (v.kind == 0) {
+        const uint64_t n_vox = (uint64_t)v.L * v.R * v.R * v.R, n_words = (n_vox + 31) / 32;
+        dense_pack_kernel<<<(unsigned)((n_words + 255) / 256), 256, 0, s>>>(occ, n_vox, (uint32_t *)v.bits, n_words);
+        OGV_CHECK_LAUNCH();
+        grid->build_stream = s;
+        return OGV_OK;
+    }
+    if (!grid->state) OGV_FAIL(OGV_ERR_INVALID, "grid has no build state");
+    const hipError_t e = enqueue_vdb(grid, *(const VdbBuildState *)grid->state, occ, s);
+    if (e != hipSuccess) OGV_FAIL(OGV_ERR_HIP, std::string("VDB refresh failed: ") + hipGetErrorString(e));
+    grid->counts_ready = false;   // ogv_grid_info_get waits for this stream and re-reads them
+    grid->build_stream = s;
+    return OGV_OK;
 }

@@ -77,8 +77,9 @@ struct ogv_grid {
     ogv::VdbCounts *counts_dev = nullptr;
     ogv::VdbCounts counts_host{};
     bool counts_ready = false;
-    hipStream_t build_stream = nullptr;
+    hipStream_t build_stream = nullptr;   // stream of the last build or refresh
     float boxes_host[ogv::kMaxLevels][6];
+    void *state = nullptr;                // VDB: build scratch and layout, kept for refreshes
 };
 
 namespace ogv {

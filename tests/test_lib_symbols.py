@@ -83,3 +83,9 @@ def test_render_blobs_validates_the_field_on_host():
         f = api.blob_field(centres, radii, dens, [[1, 1, 1]] * len(centres))
         assert lib.ogv_render_blobs(None, 0, None, None, None, None, ctypes.byref(f), None, None, None) == -1
     assert lib.ogv_render_blobs(None, 0, None, None, None, None, None, None, None, None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_refresh_rejects_null_arguments_on_host():
+    from paper_2404_10272_amd import api
+    assert api.lib().ogv_grid_refresh(None, None, None) == -1
