@@ -295,7 +295,9 @@ def main():
         plain = Timed(api, torch, dense, w, o, d, "branch", W)
         plain_skip = Timed(api, torch, dense, w, o, d, "skip", W)
         plain_rows = Timed(api, torch, dense, w, o, d, "branch", 0)
-        assert hdda.S == plain.S == hdda_other.S == plain_skip.S, "samplers disagree on the sample count"
+        distg = api.build_dist(occ, w.boxes)
+        chess = Timed(api, torch, distg, w, o, d, "branch", W)
+        assert hdda.S == plain.S == hdda_other.S == plain_skip.S == chess.S, "samplers disagree on the sample count"
         N_ = w.n_rays
 
         def rec(t):
@@ -309,6 +311,8 @@ def main():
         compare["dense"]["samples_per_s"] = plain.S / (compare["dense"]["ms_per_step"] * 1e-3)
         compare["dense_skip"] = rec(plain_skip)
         compare["dense_row_major_lanes"] = rec(plain_rows)
+        # dense bitfield + capped chessboard distances (skips the empty cube around an empty voxel)
+        compare["chessboard"] = dict(rec(chess), bytes=distg.info()["bytes"])
         compare["speedup_vs_dense"] = compare["dense"]["ms_per_step"] / ms
     count_ms = walk_ms + scan_ms
     N, S = w.n_rays, hdda.S

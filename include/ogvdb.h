@@ -109,6 +109,21 @@ typedef struct {
 ogv_status ogv_dense_build(int32_t n_levels, int32_t res, const float *boxes_host, const uint8_t *occ_dev,
                            ogv_grid **out, void *stream);
 
+/* The dense bitfield plus, per voxel, its Chebyshev (chessboard) distance to
+ * the nearest occupied voxel of its level, capped at 16 (uint8 [L][R][R][R]).
+ * Sampling on it skips, from an empty voxel at distance d >= 2, the whole
+ * cube of voxels within d - 1 in one step: the distance-field skipping the
+ * paper discusses as an alternative and does not evaluate (Sec. 2.3, Fig. 1;
+ * it notes the memory cost, here one byte per voxel).  Its
+ * samples are the dense and VDB grids' exactly.  Batches march it by its
+ * bitfield.  Same arguments and errors as ogv_dense_build. */
+ogv_status ogv_dist_build(int32_t n_levels, int32_t res, const float *boxes_host, const uint8_t *occ_dev,
+                          ogv_grid **out, void *stream);
+
+/* Copies a distance grid's capped distances (uint8 [L][R][R][R], 0 for an
+ * occupied voxel) to out_dev; OGV_ERR_INVALID for other grids. */
+ogv_status ogv_grid_distances(const ogv_grid *grid, uint8_t *out_dev, void *stream);
+
 /* VDB tree of the occupancy grid (Sec. 3): per level a dense root table of
  * internal nodes, each covering 2^internal_log2 leaf blocks of 8^3 voxels
  * per axis, with child and value bitmasks; 8^3 leaves hold 512-bit masks.

@@ -18,6 +18,7 @@ import numpy as np
 
 from .composite import composite_forward, composite_backward, composite_loss_grad  # noqa: F401
 from .render import blob_field, render_blobs  # noqa: F401
+from .distance import chessboard_distance, chessboard_distance_brute  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libogoracle.so")

@@ -68,6 +68,8 @@ VP, I32, I64, F32, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.
 SIGNATURES = {
     "ogv_dense_build": (I32, [I32, I32, VP, VP, ctypes.POINTER(VP), VP]),
     "ogv_vdb_build": (I32, [I32, I32, VP, VP, I32, ctypes.POINTER(VP), VP]),
+    "ogv_dist_build": (I32, [I32, I32, VP, VP, ctypes.POINTER(VP), VP]),
+    "ogv_grid_distances": (I32, [VP, VP, VP]),
     "ogv_grid_info_get": (I32, [VP, ctypes.POINTER(_Info)]),
     "ogv_grid_to_dense": (I32, [VP, VP, VP]),
     "ogv_grid_destroy": (None, [VP]),
@@ -174,6 +176,12 @@ class Grid:
         _check(lib().ogv_grid_refresh(self._h, _ptr(occ), _stream(stream)))
         self._occ_in_use = occ
 
+    def distances(self):
+        """A distance grid's capped chessboard distances, uint8 [L][R][R][R]."""
+        out = torch.empty(tuple(self.shape), dtype=torch.uint8, device="cuda")
+        _check(lib().ogv_grid_distances(self._h, _ptr(out), _stream()))
+        return out
+
     def close(self):
         if self._h:
             lib().ogv_grid_destroy(self._h)
@@ -204,6 +212,14 @@ def build_dense(occ, boxes, stream=None):
     h = ctypes.c_void_p()
     _check(lib().ogv_dense_build(L, R, b, _ptr(occ), ctypes.byref(h), _stream(stream)))
     return Grid(h, "dense", boxes, tuple(occ.shape))
+
+
+def build_dist(occ, boxes, stream=None):
+    """Dense bitfield plus capped chessboard distances (a third traversal)."""
+    occ, L, R, b = _grid_args(occ, boxes)
+    h = ctypes.c_void_p()
+    _check(lib().ogv_dist_build(L, R, b, _ptr(occ), ctypes.byref(h), _stream(stream)))
+    return Grid(h, "dist", boxes, tuple(occ.shape))
 
 
 def build_vdb(occ, boxes, internal_log2=4, stream=None):

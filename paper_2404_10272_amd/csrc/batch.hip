@@ -91,8 +91,9 @@ __global__ void __launch_bounds__(kBlock) batch_count_kernel(const SceneDesc *__
             load_ray(sc->o, sc->d, r, o, d);
             const int64_t gr = sc->first + r;
             CountVis vis = make_count_vis(gr, pool);
-            if (g.kind == 1) trace_ray<true, kSkip>(g, tree, o, d, lat, vis, ctx);
-            else trace_ray<false, kSkip>(g, tree, o, d, lat, vis, ctx);
+            // batches march a distance grid (kind 2) by its bitfield, as a dense grid
+            if (g.kind == 1) trace_ray<1, kSkip>(g, tree, o, d, lat, vis, ctx);
+            else trace_ray<0, kSkip>(g, tree, o, d, lat, vis, ctx);
             vis.finish(ctx);
             counts[gr] = vis.n;
             nruns[gr] = vis.nr;
@@ -124,8 +125,8 @@ __device__ __forceinline__ void batch_fill_lost(const SceneDesc *__restrict__ sc
         vis.idx = first_out;
         vis.ray = (int32_t)gr;
         vis.lev = 0;
-        if (g.kind == 1) trace_ray<true, kSkip>(g, tree, o, d, lat, vis, ctx);
-        else trace_ray<false, kSkip>(g, tree, o, d, lat, vis, ctx);
+        if (g.kind == 1) trace_ray<1, kSkip>(g, tree, o, d, lat, vis, ctx);
+        else trace_ray<0, kSkip>(g, tree, o, d, lat, vis, ctx);
     }
 }
 

@@ -87,6 +87,44 @@ __global__ void dense_unpack_kernel(const uint32_t *__restrict__ bits, uint64_t 
     out[i] = (bits[i >> 5] >> (i & 31)) & 1u;
 }
 
+// ------------------------------------------------------------------ distances
+
+// Chebyshev (chessboard) distance from every voxel of a level to the nearest
+// occupied voxel of that level, capped at kDistCap, by three separable passes:
+// along x the distance to the nearest occupied voxel of the row; along y and
+// then z, d(v) = min over |e| <= cap of max(|e|, d(v + e along the axis)).
+// Capping each pass keeps the result exactly min(cap, distance).  Voxels
+// outside the grid count as empty.  One thread per voxel; the search walks
+// outwards and stops once |e| reaches the best value found.
+template <int kAxis>
+__global__ void __launch_bounds__(256) dist_pass_kernel(const uint8_t *__restrict__ in, int L, int R,
+                                                       uint8_t *__restrict__ out) {
+    const uint64_t n = (uint64_t)L * R * R * R;
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int z = (int)(i % R), y = (int)((i / R) % R), x = (int)((i / ((uint64_t)R * R)) % R);
+    const int c = kAxis == 0 ? x : (kAxis == 1 ? y : z);
+    const int64_t stride = kAxis == 0 ? (int64_t)R * R : (kAxis == 1 ? R : 1);
+    auto val = [&](int e) -> int {   // this pass's input at offset e along the axis (in the grid)
+        const uint8_t v = in[(int64_t)i + e * stride];
+        return kAxis == 0 ? (v != 0 ? 0 : kDistCap) : (int)v;
+    };
+    int best = val(0);
+    for (int e = 1; e < best && e <= kDistCap; ++e) {
+        if (c + e < R) best = min(best, max(e, val(e)));
+        if (c - e >= 0) best = min(best, max(e, val(-e)));
+    }
+    out[i] = (uint8_t)min(best, kDistCap);
+}
+
+void enqueue_dist(const uint8_t *occ, int L, int R, uint8_t *dist, uint8_t *tmp, hipStream_t s) {
+    const uint64_t n = (uint64_t)L * R * R * R;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    dist_pass_kernel<0><<<blocks, 256, 0, s>>>(occ, L, R, dist);
+    dist_pass_kernel<1><<<blocks, 256, 0, s>>>(dist, L, R, tmp);
+    dist_pass_kernel<2><<<blocks, 256, 0, s>>>(tmp, L, R, dist);
+}
+
 // ------------------------------------------------------------------ vdb
 
 struct BuildDims {
@@ -386,6 +424,64 @@ extern "C" ogv_status ogv_dense_build(int32_t L, int32_t R, const float *boxes, 
     return OGV_OK;
 }
 
+extern "C" ogv_status ogv_dist_build(int32_t L, int32_t R, const float *boxes, const uint8_t *occ, ogv_grid **out,
+                                     void *stream) {
+    ogv_status st = check_common(L, R, boxes, occ, out);
+    if (st != OGV_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const uint64_t n_vox = (uint64_t)L * R * R * R, n_words = (n_vox + 31) / 32;
+    const size_t off_boxes = 0, off_geom = 512, off_bits = 1024;
+    const size_t off_dist = align_up(off_bits + n_words * 4, 256);
+    const size_t off_tmp = align_up(off_dist + n_vox, 256);
+    const size_t total = off_tmp + n_vox;
+    ogv_grid *g = new ogv_grid();
+    if (hipMalloc(&g->mem, total) != hipSuccess) {
+        delete g;
+        OGV_FAIL(OGV_ERR_OOM, "device allocation of " + std::to_string(total) + " bytes failed");
+    }
+    g->mem_bytes = total;
+    g->used_bytes = n_words * 4 + n_vox;
+    std::memcpy(g->boxes_host, boxes, sizeof(float) * 6 * L);
+    g->build_stream = s;
+    GridView &v = g->view;
+    std::memset(&v, 0, sizeof(v));
+    v.kind = 2;
+    v.L = L;
+    v.R = R;
+    char *m = (char *)g->mem;
+    v.boxes = (const float *)(m + off_boxes);
+    v.geom = (const float *)(m + off_geom);
+    v.bits = (const uint32_t *)(m + off_bits);
+    v.dist = (const uint8_t *)(m + off_dist);
+    g->state = m + off_tmp;   // the distance passes' scratch, kept for refreshes
+    hipError_t e = hipMemcpyAsync((void *)v.boxes, g->boxes_host, sizeof(float) * 6 * L, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        geom_kernel<<<1, 64, 0, s>>>(v.boxes, L, R, (float *)v.geom);
+        dense_pack_kernel<<<(unsigned)((n_words + 255) / 256), 256, 0, s>>>(occ, n_vox, (uint32_t *)v.bits, n_words);
+        enqueue_dist(occ, L, R, (uint8_t *)v.dist, (uint8_t *)g->state, s);
+        e = hipGetLastError();
+    }
+    // the host copy of the boxes must outlive the async copy
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(g->mem);
+        delete g;
+        OGV_FAIL(OGV_ERR_HIP, std::string("distance-grid build failed: ") + hipGetErrorString(e));
+    }
+    g->counts_ready = true;
+    *out = g;
+    return OGV_OK;
+}
+
+extern "C" ogv_status ogv_grid_distances(const ogv_grid *grid, uint8_t *out, void *stream) {
+    if (!grid || !out) OGV_FAIL(OGV_ERR_INVALID, "null argument");
+    const GridView &v = grid->view;
+    if (v.kind != 2) OGV_FAIL(OGV_ERR_INVALID, "only a distance grid holds distances");
+    const size_t n = (size_t)v.L * v.R * v.R * v.R;
+    OGV_CHECK_HIP(hipMemcpyAsync(out, v.dist, n, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return OGV_OK;
+}
+
 extern "C" ogv_status ogv_vdb_build(int32_t L, int32_t R, const float *boxes, const uint8_t *occ, int32_t ilog2,
                                     ogv_grid **out, void *stream) {
     ogv_status st = check_common(L, R, boxes, occ, out);
@@ -509,7 +605,7 @@ extern "C" ogv_status ogv_grid_info_get(const ogv_grid *grid, ogv_grid_info *inf
     info->n_levels = v.L;
     info->res = v.R;
     info->internal_log2 = v.ilog2;
-    if (v.kind == 0) {
+    if (v.kind != 1) {
         info->bytes = (int64_t)g->used_bytes;
         return OGV_OK;
     }
@@ -538,7 +634,7 @@ extern "C" ogv_status ogv_grid_to_dense(const ogv_grid *grid, uint8_t *out, void
     uint64_t n_vox = (uint64_t)v.L * v.R * v.R * v.R;
     hipStream_t s = (hipStream_t)stream;
     unsigned blocks = (unsigned)((n_vox + 255) / 256);
-    if (v.kind == 0) dense_unpack_kernel<<<blocks, 256, 0, s>>>(v.bits, n_vox, out);
+    if (v.kind != 1) dense_unpack_kernel<<<blocks, 256, 0, s>>>(v.bits, n_vox, out);
     else vdb_unpack_kernel<<<blocks, 256, 0, s>>>(v, out);
     OGV_CHECK_LAUNCH();
     return OGV_OK;
@@ -546,7 +642,7 @@ extern "C" ogv_status ogv_grid_to_dense(const ogv_grid *grid, uint8_t *out, void
 
 extern "C" void ogv_grid_destroy(ogv_grid *grid) {
     if (!grid) return;
-    free_state(grid);
+    if (grid->view.kind == 1) free_state(grid);   // a kind-2 grid's state points into its own allocation
     (void)hipFree(grid->mem);
     delete grid;
 }
@@ -555,9 +651,10 @@ extern "C" ogv_status ogv_grid_refresh(ogv_grid *grid, const uint8_t *occ, void 
     if (!grid || !occ) OGV_FAIL(OGV_ERR_INVALID, "null argument");
     hipStream_t s = (hipStream_t)stream;
     GridView &v = grid->view;
-    if (v.kind == 0) {
+    if (v.kind == 0 || v.kind == 2) {
         const uint64_t n_vox = (uint64_t)v.L * v.R * v.R * v.R, n_words = (n_vox + 31) / 32;
         dense_pack_kernel<<<(unsigned)((n_words + 255) / 256), 256, 0, s>>>(occ, n_vox, (uint32_t *)v.bits, n_words);
+        if (v.kind == 2) enqueue_dist(occ, v.L, v.R, (uint8_t *)v.dist, (uint8_t *)grid->state, s);
         OGV_CHECK_LAUNCH();
         grid->build_stream = s;
         return OGV_OK;

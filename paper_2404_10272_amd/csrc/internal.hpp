@@ -47,7 +47,7 @@ constexpr int kMaxLevels = OGV_MAX_LEVELS;
 // with S = 2^ilog2 slots per axis per node, slot s = (sx*S + sy)*S + sz,
 // W = ceil(S^3 / 64) words per mask.  A root cell covers D = 8*S voxels.
 struct GridView {
-    int32_t kind;      // 0 dense bitfield, 1 VDB tree
+    int32_t kind;      // 0 dense bitfield, 1 VDB tree, 2 dense bitfield + chessboard distances
     int32_t L, R;
     int32_t ilog2, S, NR, W;
     const float *boxes;        // [L][6] device copy of the boxes
@@ -59,7 +59,12 @@ struct GridView {
     const uint32_t *rank;
     const int32_t *slot;
     const uint64_t *leaves;
+    const uint8_t *dist;       // kind 2: per voxel min(kDistCap, Chebyshev distance to the nearest occupied voxel)
 };
+
+// Cap of the chessboard distances a kind-2 grid stores: an empty voxel at
+// distance d >= 2 (d <= kDistCap) has every voxel within d - 1 of it empty.
+constexpr int kDistCap = 16;
 
 struct VdbCounts {             // device-side counters filled by the build
     int64_t n_nodes, n_leaves;

@@ -48,14 +48,14 @@ __device__ __forceinline__ void add_tile_sums(int64_t ray, int32_t n, int64_t *_
 // run pool ran dry, the traversal fill writes the ray); the runs themselves
 // go to the pool's slots and chunks; tile_sums[k] gains the counts of rays
 // k*kScanTile .. (k+1)*kScanTile-1.
-template <bool kVdb, bool kSkip, bool kLds, bool kL1>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(!kVdb && kL1 ? 8 : 1))) count_kernel(GridView g, const float *__restrict__ origins,
+template <int kGrid, bool kSkip, bool kLds, bool kL1>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kGrid == 0 && kL1 ? 8 : 1))) count_kernel(GridView g, const float *__restrict__ origins,
                                                        const float *__restrict__ dirs, int64_t n_rays, Lattice lat,
                                                        int32_t *__restrict__ counts, int32_t *__restrict__ nruns,
                                                        RunPool pool, int image_width,
                                                        int64_t *__restrict__ tile_sums) {
     extern __shared__ uint32_t smem[];
-    Tree tree = kVdb ? load_tree<kLds>(g, smem) : Tree{};
+    Tree tree = kGrid == 1 ? load_tree<kLds>(g, smem) : Tree{};
     const int64_t i = ray_of_thread((int64_t)blockIdx.x * kBlock + threadIdx.x, n_rays, image_width);
     int32_t n = 0;
     if (i >= 0) {
@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(!kV
         load_ray(origins, dirs, i, o, d);
         const CountCtx ctx{lat, pool};
         CountVis vis = make_count_vis(i, pool);
-        trace_ray<kVdb, kSkip, kL1>(g, tree, o, d, lat, vis, ctx);
+        trace_ray<kGrid, kSkip, kL1>(g, tree, o, d, lat, vis, ctx);
         vis.finish(ctx);
         n = vis.n;
         counts[i] = n;
@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(!kV
 // every ray (list == nullptr; used when voxel ids are requested), or the
 // *list_len rays of `list` (the rays whose runs the count pass could not
 // keep), over a grid that strides through the list.
-template <bool kVdb, bool kSkip, bool kVox, bool kLds>
+template <int kGrid, bool kSkip, bool kVox, bool kLds>
 __global__ void __launch_bounds__(kBlock) fill_kernel(GridView g, const float *__restrict__ origins,
                                                       const float *__restrict__ dirs, int64_t n_rays, Lattice lat,
                                                       const int64_t *__restrict__ offsets, int64_t capacity,
@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(kBlock) fill_kernel(GridView g, const float *_
     extern __shared__ uint32_t smem[];
     const int64_t m = list ? (int64_t)*list_len : n_rays;
     if ((int64_t)blockIdx.x * kBlock >= m) return;   // block-uniform: no work, skip the staging too
-    Tree tree = kVdb ? load_tree<kLds>(g, smem) : Tree{};
+    Tree tree = kGrid == 1 ? load_tree<kLds>(g, smem) : Tree{};
     const FillCtx ctx{lat, capacity, ray_ids, t0, t1, vox, g.R};
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < m; k += (int64_t)gridDim.x * kBlock) {
         const int64_t i = list ? (int64_t)list[k] : k;
@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(kBlock) fill_kernel(GridView g, const float *_
         vis.idx = first;
         vis.ray = (int32_t)i;
         vis.lev = 0;
-        trace_ray<kVdb, kSkip>(g, tree, o, d, lat, vis, ctx);
+        trace_ray<kGrid, kSkip>(g, tree, o, d, lat, vis, ctx);
     }
 }
 
@@ -119,7 +119,7 @@ __global__ void pool_reset_kernel(int32_t *head, int64_t *tile_sums, int64_t n_t
 // blocks stride through their list, reading the tree from global memory.
 // Those outputs are disjoint from the expansion's (it skips them, and a
 // 16-byte group they share is written with 4-byte stores).
-template <bool kVdb, bool kSkip>
+template <int kGrid, bool kSkip>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kExpandWaves))) expand_kernel(GridView g, const float *__restrict__ origins,
                                                         const float *__restrict__ dirs,
                                                         const int64_t *__restrict__ offsets, int64_t n_rays,
@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kEx
     expand_block(offsets, n_rays, nruns, rd, OneLattice{lat}, capacity, ray_ids, t0, t1, vec4 != 0);
     const int64_t m = *n_lost;
     if (m == 0) return;
-    const Tree tree = kVdb ? load_tree<false>(g, nullptr) : Tree{};
+    const Tree tree = kGrid == 1 ? load_tree<false>(g, nullptr) : Tree{};
     const FillCtx ctx{lat, capacity, ray_ids, t0, t1, nullptr, g.R};
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < m; k += (int64_t)gridDim.x * kBlock) {
         const int64_t i = lost[k];
@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kEx
         vis.idx = first;
         vis.ray = (int32_t)i;
         vis.lev = 0;
-        trace_ray<kVdb, kSkip>(g, tree, o, d, lat, vis, ctx);
+        trace_ray<kGrid, kSkip>(g, tree, o, d, lat, vis, ctx);
     }
 }
 
@@ -387,7 +387,7 @@ RunReader reader_of(const Bufs &b) {
     return RunReader{b.pool.slots, b.pool.stride, b.pool.ray_next, b.pool.chunks, b.pool.chunk_next};
 }
 
-template <bool kVdb, bool kSkip, bool kLds>
+template <int kGrid, bool kSkip, bool kLds>
 void launch_count(const GridView &g, const float *o, const float *d, int64_t n, const Lattice &lat, const Bufs &b,
                   int width, hipStream_t s) {
     unsigned blocks = (unsigned)((tiled_threads(n, width) + kBlock - 1) / kBlock);
@@ -395,17 +395,17 @@ void launch_count(const GridView &g, const float *o, const float *d, int64_t n, 
     const int64_t nt = scan_tiles(n);
     pool_reset_kernel<<<(unsigned)std::min<int64_t>((nt + 255) / 256 + 1, 64), 256, 0, s>>>(b.pool.head, b.tiles, nt);
     if (g.L == 1)
-        count_kernel<kVdb, kSkip, kLds, true>
+        count_kernel<kGrid, kSkip, kLds, true>
             <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool, width, b.tiles);
     else
-        count_kernel<kVdb, kSkip, kLds, false>
+        count_kernel<kGrid, kSkip, kLds, false>
             <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool, width, b.tiles);
 }
 
 // Lost-ray fills run on a small grid that strides through the list.
 constexpr unsigned kListBlocks = 64;
 
-template <bool kVdb, bool kSkip, bool kLds>
+template <int kGrid, bool kSkip, bool kLds>
 void launch_fill(const GridView &g, const float *o, const float *d, int64_t n, const Lattice &lat,
                  const int64_t *offsets, int64_t cap, int32_t *ids, float *t0, float *t1, int32_t *vox,
                  const int32_t *list, const int32_t *list_len, hipStream_t s) {
@@ -413,10 +413,10 @@ void launch_fill(const GridView &g, const float *o, const float *d, int64_t n, c
     if (list) blocks = std::min(blocks, kListBlocks);
     size_t shm = kLds ? lds_bytes(g) : 0;
     if (vox)
-        fill_kernel<kVdb, kSkip, true, kLds>
+        fill_kernel<kGrid, kSkip, true, kLds>
             <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, offsets, cap, ids, t0, t1, vox, list, list_len);
     else
-        fill_kernel<kVdb, kSkip, false, kLds>
+        fill_kernel<kGrid, kSkip, false, kLds>
             <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, offsets, cap, ids, t0, t1, vox, list, list_len);
 }
 
@@ -424,14 +424,17 @@ void dispatch_count(const GridView &g, int variant, const float *o, const float 
                     const Bufs &b, int width, hipStream_t s) {
     const bool lds = lds_bytes(g) <= kLdsTreeBytes;
     if (g.kind == 0) {
-        if (variant == OGV_SKIP) launch_count<false, true, false>(g, o, d, n, lat, b, width, s);
-        else launch_count<false, false, false>(g, o, d, n, lat, b, width, s);
+        if (variant == OGV_SKIP) launch_count<0, true, false>(g, o, d, n, lat, b, width, s);
+        else launch_count<0, false, false>(g, o, d, n, lat, b, width, s);
+    } else if (g.kind == 2) {
+        if (variant == OGV_SKIP) launch_count<2, true, false>(g, o, d, n, lat, b, width, s);
+        else launch_count<2, false, false>(g, o, d, n, lat, b, width, s);
     } else if (lds) {
-        if (variant == OGV_SKIP) launch_count<true, true, true>(g, o, d, n, lat, b, width, s);
-        else launch_count<true, false, true>(g, o, d, n, lat, b, width, s);
+        if (variant == OGV_SKIP) launch_count<1, true, true>(g, o, d, n, lat, b, width, s);
+        else launch_count<1, false, true>(g, o, d, n, lat, b, width, s);
     } else {
-        if (variant == OGV_SKIP) launch_count<true, true, false>(g, o, d, n, lat, b, width, s);
-        else launch_count<true, false, false>(g, o, d, n, lat, b, width, s);
+        if (variant == OGV_SKIP) launch_count<1, true, false>(g, o, d, n, lat, b, width, s);
+        else launch_count<1, false, false>(g, o, d, n, lat, b, width, s);
     }
 }
 
@@ -441,14 +444,17 @@ void dispatch_fill(const GridView &g, int variant, const float *o, const float *
     const bool lds = lds_bytes(g) <= kLdsTreeBytes;
 #define OGV_FILL(V, K, L) launch_fill<V, K, L>(g, o, d, n, lat, offsets, cap, ids, t0, t1, vox, list, list_len, s)
     if (g.kind == 0) {
-        if (variant == OGV_SKIP) OGV_FILL(false, true, false);
-        else OGV_FILL(false, false, false);
+        if (variant == OGV_SKIP) OGV_FILL(0, true, false);
+        else OGV_FILL(0, false, false);
+    } else if (g.kind == 2) {
+        if (variant == OGV_SKIP) OGV_FILL(2, true, false);
+        else OGV_FILL(2, false, false);
     } else if (lds) {
-        if (variant == OGV_SKIP) OGV_FILL(true, true, true);
-        else OGV_FILL(true, false, true);
+        if (variant == OGV_SKIP) OGV_FILL(1, true, true);
+        else OGV_FILL(1, false, true);
     } else {
-        if (variant == OGV_SKIP) OGV_FILL(true, true, false);
-        else OGV_FILL(true, false, false);
+        if (variant == OGV_SKIP) OGV_FILL(1, true, false);
+        else OGV_FILL(1, false, false);
     }
 #undef OGV_FILL
 }
@@ -499,11 +505,14 @@ ogv_status fill_all(const ogv_grid *grid, int32_t variant, const float *o, const
     expand_kernel<V, K><<<blocks, kBlock, 0, s>>>(g, o, d, offsets, n, b.nruns, reader_of(b), lat, cap, ids, t0, t1, \
                                                    vec4, b.pool.lost, b.pool.n_lost)
     if (g.kind == 0) {
-        if (variant == OGV_SKIP) OGV_EXPAND(false, true);
-        else OGV_EXPAND(false, false);
+        if (variant == OGV_SKIP) OGV_EXPAND(0, true);
+        else OGV_EXPAND(0, false);
+    } else if (g.kind == 2) {
+        if (variant == OGV_SKIP) OGV_EXPAND(2, true);
+        else OGV_EXPAND(2, false);
     } else {
-        if (variant == OGV_SKIP) OGV_EXPAND(true, true);
-        else OGV_EXPAND(true, false);
+        if (variant == OGV_SKIP) OGV_EXPAND(1, true);
+        else OGV_EXPAND(1, false);
     }
 #undef OGV_EXPAND
     OGV_CHECK_LAUNCH();

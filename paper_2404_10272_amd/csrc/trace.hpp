@@ -440,26 +440,108 @@ struct FillVis {
     }
 };
 
+// Dense bitfield with chessboard distances (a traversal the paper discusses
+// but does not evaluate, Sec. 2.3 and Fig. 1): in an empty voxel at distance d >= 2 from
+// every occupied voxel, the whole cube of voxels within d - 1 of it is empty,
+// so the ray leaves that cube in one step.  The cube's exit planes are the
+// current voxel's ray-order index plus d per axis; after the exit, the axes
+// it did not leave through are re-located exactly at the exit parameter
+// within the cube (the search the VDB walk uses on descent).  Occupied voxels
+// and empty ones at distance 1 are single cells, stepped as by the dense
+// march.
+struct DistCursor {
+    const uint32_t *bits;
+    const uint8_t *dist;
+    uint64_t level_base;   // index of the level's voxel (0,0,0)
+    int R;
+    Axis A0, A1, A2;
+    int u0, u1, u2;        // ray-order voxel per moving axis
+    int v0, v1, v2;        // voxel index per axis
+    int k0, k1, k2;        // ray-order exit plane of the current cell per moving axis
+    float e0, e1, e2;      // their crossing parameters (+inf for zero axes)
+    int kx;                // exit plane of the axis exit() chose
+    int h;                 // the current cell reaches h voxels past the current voxel (0: a single voxel)
+    bool occ;
+
+    __device__ __forceinline__ void classify() {
+        const uint64_t idx = level_base + ((uint64_t)((uint32_t)v0 * (uint32_t)R + (uint32_t)v1) * (uint32_t)R + (uint32_t)v2);
+        const int d = dist[idx];
+        occ = d == 0;
+        h = d >= 2 ? d - 1 : 0;
+    }
+    __device__ __forceinline__ void exits_all() {
+        const float inf = __builtin_huge_valf();
+        e0 = e1 = e2 = inf;
+        if (!A0.zero) { k0 = min(u0 + h + 1, R); e0 = A0.Tk(k0); }
+        if (!A1.zero) { k1 = min(u1 + h + 1, R); e1 = A1.Tk(k1); }
+        if (!A2.zero) { k2 = min(u2 + h + 1, R); e2 = A2.Tk(k2); }
+    }
+    __device__ __forceinline__ void enter() {
+        classify();
+        exits_all();
+    }
+    __device__ __forceinline__ bool occupied() const { return occ; }
+    __device__ __forceinline__ float exit(int &axis) {
+        float hi = e0;
+        int k = k0;
+        axis = 0;
+        if (e1 < hi) { hi = e1; k = k1; axis = 1; }
+        if (e2 < hi) { hi = e2; k = k2; axis = 2; }
+        kx = k;
+        return hi;
+    }
+    __device__ __forceinline__ bool step(int axis, float t) {
+        const int ka = kx;
+        if (ka >= R) return false;
+        const int h_old = h;
+        if (axis == 0) { u0 = ka; v0 = A0.voxel(ka); }
+        if (axis == 1) { u1 = ka; v1 = A1.voxel(ka); }
+        if (axis == 2) { u2 = ka; v2 = A2.voxel(ka); }
+        if (h_old > 0) {
+            // out of an empty cube: the other axes' voxels at t, inside the cube
+            if (axis != 0 && !A0.zero) { u0 = A0.advance_to(u0, t, k0 - 1); v0 = A0.voxel(u0); }
+            if (axis != 1 && !A1.zero) { u1 = A1.advance_to(u1, t, k1 - 1); v1 = A1.voxel(u1); }
+            if (axis != 2 && !A2.zero) { u2 = A2.advance_to(u2, t, k2 - 1); v2 = A2.voxel(u2); }
+        }
+        classify();
+        if (h_old == 0 && h == 0) {
+            // one voxel to the next: only the stepping axis's exit moves
+            if (axis == 0) { k0 = ka + 1; e0 = A0.Tk(k0); }
+            if (axis == 1) { k1 = ka + 1; e1 = A1.Tk(k1); }
+            if (axis == 2) { k2 = ka + 1; e2 = A2.Tk(k2); }
+        } else {
+            exits_all();
+        }
+        return true;
+    }
+};
+
 // ------------------------------------------------------------------ ray
 
 struct Ray {
     float o0, o1, o2, d0, d1, d2, r0, r1, r2;
 };
 
-template <bool kVdb>
+// Grid kinds: 0 dense bitfield, 1 VDB tree, 2 dense bitfield with chessboard
+// distances (GridView::kind).
+template <int kGrid>
 struct CursorOf {
     using type = DenseCursor;
 };
 template <>
-struct CursorOf<true> {
+struct CursorOf<1> {
     using type = VdbCursor;
+};
+template <>
+struct CursorOf<2> {
+    using type = DistCursor;
 };
 
 // Puts the cursor of level `lev` on the voxel owning t_min when t_min lies
 // after the segment start a, else on the voxel owning the parameters just
 // after a.  False when that voxel is outside the grid.
-template <bool kVdb, class Vis>
-__device__ __forceinline__ bool cursor_begin(typename CursorOf<kVdb>::type &c, const GridView &g, const Tree &tree,
+template <int kGrid, class Vis>
+__device__ __forceinline__ bool cursor_begin(typename CursorOf<kGrid>::type &c, const GridView &g, const Tree &tree,
                                              int lev, const Ray &ray, float a, const Lattice &lat, Vis &vis) {
     const int R = g.R;
     Axis A0 = load_axis(g.geom, lev, 0, R, ray.o0, ray.d0, ray.r0);
@@ -479,13 +561,19 @@ __device__ __forceinline__ bool cursor_begin(typename CursorOf<kVdb>::type &c, c
     c.A0 = A0; c.A1 = A1; c.A2 = A2;
     c.u0 = u0; c.u1 = u1; c.u2 = u2;
     c.v0 = v0; c.v1 = v1; c.v2 = v2;
-    if constexpr (!kVdb) {
+    if constexpr (kGrid == 0) {
         const float inf = __builtin_huge_valf();
         c.bits = g.bits;
         c.level_base = (uint64_t)lev * R * R * R;
         c.tn0 = A0.zero ? inf : A0.Tk(u0 + 1);
         c.tn1 = A1.zero ? inf : A1.Tk(u1 + 1);
         c.tn2 = A2.zero ? inf : A2.Tk(u2 + 1);
+    } else if constexpr (kGrid == 2) {
+        c.bits = g.bits;
+        c.dist = g.dist;
+        c.level_base = (uint64_t)lev * R * R * R;
+        c.k0 = c.k1 = c.k2 = 0;
+        c.enter();
     } else {
         c.t = tree;
         c.lev = lev;
@@ -500,11 +588,11 @@ __device__ __forceinline__ bool cursor_begin(typename CursorOf<kVdb>::type &c, c
     return true;
 }
 
-template <bool kVdb, bool kSkip, class Vis, class Ctx>
+template <int kGrid, bool kSkip, class Vis, class Ctx>
 __device__ __forceinline__ void march_segment(const GridView &g, const Tree &tree, int lev, const Ray &ray, float a,
                                               float b, const Lattice &lat, Vis &vis, const Ctx &ctx) {
-    typename CursorOf<kVdb>::type c;
-    if (!cursor_begin<kVdb>(c, g, tree, lev, ray, a, lat, vis)) return;
+    typename CursorOf<kGrid>::type c;
+    if (!cursor_begin<kGrid>(c, g, tree, lev, ray, a, lat, vis)) return;
     drive<kSkip>(c, a, b, lat.tmax, vis, ctx);
 }
 
@@ -524,7 +612,7 @@ __device__ __forceinline__ bool span_of(const GridView &g, int lev, const Ray &r
 // f+(k-m) on (X_{f+k-m-1}, X_{f+k-m}].  Each segment is marched by its level.
 // kL1: the grid has a single level (no cascades), so the level geometry is
 // uniform across the wave.
-template <bool kVdb, bool kSkip, bool kL1 = false, class Vis, class Ctx>
+template <int kGrid, bool kSkip, bool kL1 = false, class Vis, class Ctx>
 __device__ __forceinline__ void trace_ray(const GridView &g, const Tree &tree, const float o[3], const float d[3],
                                           const Lattice &lat, Vis &vis, const Ctx &ctx) {
     if (!(lat.tmin <= lat.tmax)) return;
@@ -535,7 +623,7 @@ __device__ __forceinline__ void trace_ray(const GridView &g, const Tree &tree, c
     if (kL1) {
         float E, X;
         if (span_of(g, 0, ray, E, X) && E < lat.tmax && X >= lat.tmin)
-            march_segment<kVdb, kSkip>(g, tree, 0, ray, E, X, lat, vis, ctx);
+            march_segment<kGrid, kSkip>(g, tree, 0, ray, E, X, lat, vis, ctx);
         return;
     }
     const int L = g.L;
@@ -574,7 +662,7 @@ __device__ __forceinline__ void trace_ray(const GridView &g, const Tree &tree, c
         float a = k <= m ? E_l : X_i;
         float b = k < m ? E_i : X_l;
         if (a >= lat.tmax) break;   // this and every later segment lie past t_max
-        if (a < b && b >= lat.tmin) march_segment<kVdb, kSkip>(g, tree, lev, ray, a, b, lat, vis, ctx);
+        if (a < b && b >= lat.tmin) march_segment<kGrid, kSkip>(g, tree, lev, ray, a, b, lat, vis, ctx);
     }
 }
 

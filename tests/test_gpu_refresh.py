@@ -30,15 +30,17 @@ def _sample(g, o, d, w):
     return {k: v.cpu().numpy() for k, v in out.items()}
 
 
-@pytest.mark.parametrize("kind", ["vdb", "dense"])
+@pytest.mark.parametrize("kind", ["vdb", "dense", "dist"])
 def test_refresh_is_a_fresh_build(kind):
     w = scenes.workload("object")
     rng = np.random.default_rng(7002)
     pick = np.sort(rng.choice(w.n_rays, size=20000, replace=False))
     o_h, d_h = np.ascontiguousarray(w.origins[pick]), np.ascontiguousarray(w.dirs[pick])
     o, d = torch.from_numpy(o_h).cuda(), torch.from_numpy(d_h).cuda()
-    build = (lambda x: api.build_vdb(torch.from_numpy(x).cuda(), w.boxes, w.ilog2)) if kind == "vdb" else \
-        (lambda x: api.build_dense(torch.from_numpy(x).cuda(), w.boxes))
+    builders = {"vdb": lambda x: api.build_vdb(torch.from_numpy(x).cuda(), w.boxes, w.ilog2),
+                "dense": lambda x: api.build_dense(torch.from_numpy(x).cuda(), w.boxes),
+                "dist": lambda x: api.build_dist(torch.from_numpy(x).cuda(), w.boxes)}
+    build = builders[kind]
     g = build(w.occ)
     for name, occ in zip(("fewer", "more", "back"), _variants(w.occ) + (w.occ,)):
         g.refresh(torch.from_numpy(occ).cuda())
@@ -49,6 +51,8 @@ def test_refresh_is_a_fresh_build(kind):
             assert (info["n_nodes"], info["n_leaves"], info["n_tiles_full"], info["n_tiles_empty"]) == (
                 st["nodes"], st["leaves"], st["slot_full"], st["slot_empty"]), name
             print(name, info["n_leaves"], flush=True)
+        if kind == "dist":
+            np.testing.assert_array_equal(g.distances().cpu().numpy(), oracle.chessboard_distance(occ), err_msg=name)
         got = _sample(g, o, d, w)
         ref = oracle.sample_rays(oracle.Scene(occ, w.boxes), o_h, d_h, w.near, w.far, w.step, "dense_branch")
         np.testing.assert_array_equal(got["offsets"], ref["offsets"], err_msg=name)

@@ -3,8 +3,8 @@
 The bar (sample-exact): identical per-ray counts (offsets), ray ids and voxel
 ids, and t0/t1 within 1e-5 absolute in binary32 -- asserted here as bit-exact,
 which the shared binary32 definition makes reachable.  Every case runs the
-dense voxel DDA and VDB + hierarchical DDA, each as Alg. 1 (branch) and
-Alg. 2 (skip).
+dense voxel DDA, VDB + hierarchical DDA and the chessboard-distance march,
+each as Alg. 1 (branch) and Alg. 2 (skip).
 """
 import numpy as np
 import pytest
@@ -16,7 +16,8 @@ from tests import handmade
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [("dense", "branch"), ("dense", "skip"), ("vdb", "branch"), ("vdb", "skip")]
+VARIANTS = [("dense", "branch"), ("dense", "skip"), ("vdb", "branch"), ("vdb", "skip"), ("dist", "branch"),
+            ("dist", "skip")]
 _VID = lambda v: f"{v[0]}-{v[1]}"
 
 
@@ -24,6 +25,8 @@ def gpu_grid(kind, occ, boxes, ilog2):
     occ_d = torch.from_numpy(np.ascontiguousarray(occ)).cuda()
     if kind == "dense":
         return api.build_dense(occ_d, boxes)
+    if kind == "dist":
+        return api.build_dist(occ_d, boxes)
     return api.build_vdb(occ_d, boxes, ilog2)
 
 
