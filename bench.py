@@ -102,6 +102,9 @@ class Timed:
         torch.cuda.synchronize()
         total_ms = start.elapsed_time(end)
         stage = [sum(e[i].elapsed_time(e[i + 1]) for e in evs) / steps for i in range(3)]
+        per = sorted(e[0].elapsed_time(e[3]) for e in evs)   # each step alone, first event to last
+        self.step_stats = {"median_ms": per[len(per) // 2], "min_ms": per[0],
+                           "p90_ms": per[min(len(per) - 1, (9 * len(per)) // 10)]}
         return total_ms / steps, stage[0], stage[1], stage[2]
 
 
@@ -243,9 +246,22 @@ def cpu_baseline(w, stride, min_s=10.0, max_s=30.0):
         samples = int(out["offsets"][-1])
         if spent + one > max_s:
             break
+    # one thread on every 16th ray of that sample: the per-core rate
+    o1, d1 = np.ascontiguousarray(o[::16]), np.ascontiguousarray(d[::16])
+    t = time.perf_counter()
+    oracle.sample_rays(scene, o1, d1, w.near, w.far, w.step, "hdda_skip", ilog2=w.ilog2, threads=1)
+    one_s = time.perf_counter() - t
+    model = ""
+    try:
+        model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+    except Exception:
+        pass
     return {"value": reps * n / spent, "unit": "rays/s", "cores": threads, "kind": "oracle",
             "sample": f"every {stride}th ray of the workload ({n} rays, {samples} samples) x {reps} repeats, "
-                      f"VDB + hierarchical DDA (Alg. 2 loop), count + fill, {spent:.1f} s wall"}
+                      f"VDB + hierarchical DDA (Alg. 2 loop), count + fill, {spent:.1f} s wall",
+            "single_thread": {"value": o1.shape[0] / one_s, "unit": "rays/s",
+                              "sample": f"every {16 * stride}th ray ({o1.shape[0]} rays), one thread, {one_s:.1f} s"},
+            "host": {"cpus": os.cpu_count(), "model": model}}
 
 
 def main():
@@ -363,7 +379,8 @@ def main():
         "samples_per_s": S / (ms * 1e-3),
         "vdb": {"ms_per_step": ms, "count_scan_ms": count_ms, "walk_ms": walk_ms, "scan_ms": scan_ms,
                 "fill_ms": fill_ms, "rays_per_s": N / (ms * 1e-3),
-                "bytes": G, "leaves": vinfo["n_leaves"], "build_ms": build_ms, "refresh_ms": refresh_ms},
+                "bytes": G, "leaves": vinfo["n_leaves"], "build_ms": build_ms, "refresh_ms": refresh_ms,
+                "step_stats": hdda.step_stats},
         "step_bytes": step_bytes,
         "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "runs": runs,
