@@ -1,0 +1,89 @@
+"""The sampler at the size limits the header declares, against the oracle:
+a 1024^3 grid (the largest resolution; its VDB tree has 512 root cells, too
+many for the LDS, so the walk reads the tree from global memory) and eight
+nested cascade levels (the most levels).  Every grid kind, samples bit for
+bit on rays drawn through the grid."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2404_10272_amd import api, scenes
+
+pytestmark = pytest.mark.gpu
+
+BUILD = {"vdb": lambda occ, boxes: api.build_vdb(occ, boxes, 4),
+         "dense": lambda occ, boxes: api.build_dense(occ, boxes),
+         "dist": lambda occ, boxes: api.build_dist(occ, boxes)}
+
+
+def _assert_same(got, ref, what):
+    for k in ("offsets", "ray_ids", "t0", "t1"):
+        np.testing.assert_array_equal(got[k], ref[k], err_msg=f"{what} {k}")
+
+
+def _largest_grid():
+    """1024^3 over [-1,1]^3: three solid balls (full tiles inside) and three
+    thin spherical shells (leaves along them), built on the GPU in slabs."""
+    R = 1024
+    rng = np.random.default_rng(8101)
+    c = (torch.arange(R, device="cuda", dtype=torch.float32) + 0.5) / R * 2.0 - 1.0
+    occ = torch.zeros((1, R, R, R), dtype=torch.uint8, device="cuda")
+    shapes = [(rng.uniform(-0.5, 0.5, 3), rng.uniform(0.15, 0.35), k >= 3) for k in range(6)]
+    for x0 in range(0, R, 64):
+        X = c[x0:x0 + 64, None, None]
+        Y = c[None, :, None]
+        Z = c[None, None, :]
+        for ctr, rad, shell in shapes:
+            d2 = (X - float(ctr[0])) ** 2 + (Y - float(ctr[1])) ** 2 + (Z - float(ctr[2])) ** 2
+            m = (d2.sqrt() - rad).abs() < 0.004 if shell else d2 < rad * rad
+            occ[0, x0:x0 + 64] |= m.to(torch.uint8)
+    return occ, np.asarray([[-1.0, -1.0, -1.0, 1.0, 1.0, 1.0]], np.float32)
+
+
+@pytest.fixture(scope="module")
+def largest():
+    occ_d, boxes = _largest_grid()
+    occ = occ_d.cpu().numpy()
+    rng = np.random.default_rng(8102)
+    o, d = scenes.random_rays(4096, rng, -1.6, 1.6)
+    step = oracle.make_step("const", dt=1e-3)
+    ref = oracle.sample_rays(oracle.Scene(occ, boxes), o, d, 0.0, 6.0, step, "dense_branch")
+    return occ_d, occ, boxes, o, d, step, ref
+
+
+@pytest.mark.parametrize("kind", ["vdb", "dense", "dist"])
+def test_largest_resolution(largest, kind):
+    occ_d, occ, boxes, o, d, step, ref = largest
+    assert ref["offsets"][-1] > 10000
+    g = BUILD[kind](occ_d, boxes)
+    if kind == "vdb":
+        info = g.info()
+        st = oracle.Scene(occ, boxes).vdb_stats(4)
+        assert (info["n_nodes"], info["n_leaves"]) == (st["nodes"], st["leaves"])
+        print("leaves", info["n_leaves"], "nodes", info["n_nodes"], flush=True)
+    for variant in ("branch", "skip"):
+        out = api.sample_rays(g, torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), 0.0, 6.0,
+                              api.make_step(step), variant)
+        torch.cuda.synchronize()
+        _assert_same({k: v.cpu().numpy() for k, v in out.items()}, ref, f"1024^3 {kind} {variant}")
+
+
+@pytest.mark.parametrize("kind", ["vdb", "dense", "dist"])
+def test_most_levels(kind):
+    L, R = 8, 16
+    rng = np.random.default_rng(8103)
+    occ = (rng.random((L, R, R, R)) < 0.04).astype(np.uint8)
+    boxes = np.asarray([[-2.0 ** k] * 3 + [2.0 ** k] * 3 for k in range(L)], np.float32)
+    o = rng.uniform(-0.5, 0.5, (3000, 3)).astype(np.float32)
+    d = rng.normal(size=(3000, 3))
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    step = oracle.make_step("cone", cone=1 / 64, dt_min=0.01)
+    ref = oracle.sample_rays(oracle.Scene(occ, boxes), o, d, 0.05, 400.0, step, "dense_branch")
+    assert ref["offsets"][-1] > 10000
+    g = BUILD[kind](torch.from_numpy(occ).cuda(), boxes) if kind != "vdb" else \
+        api.build_vdb(torch.from_numpy(occ).cuda(), boxes, 1)
+    out = api.sample_rays(g, torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), 0.05, 400.0,
+                          api.make_step(step), "branch")
+    torch.cuda.synchronize()
+    _assert_same({k: v.cpu().numpy() for k, v in out.items()}, ref, f"8 levels {kind}")
