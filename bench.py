@@ -154,8 +154,11 @@ def cascades_side(api, torch, scenes, steps, warmup):
     for name, grid in (("vdb", api.build_vdb(occ, w.boxes, w.ilog2)), ("dense", api.build_dense(occ, w.boxes))):
         t = Timed(api, torch, grid, w, o, d, "branch", w.image[0])
         ms, walk, scan, fill = t.run(steps, warmup)
+        N, S, G = w.n_rays, t.S, grid.info()["bytes"]
+        step_bytes = 24 * N + 8 * (N + 1) + 12 * S + G   # the call's inputs and outputs, as for the headline
         out[name] = {"ms_per_step": ms, "walk_ms": walk, "scan_ms": scan, "fill_ms": fill,
-                     "rays_per_s": w.n_rays / (ms * 1e-3), "samples": t.S}
+                     "rays_per_s": N / (ms * 1e-3), "samples_per_s": S / (ms * 1e-3), "samples": S,
+                     "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del t
     out["speedup_vs_dense"] = out["dense"]["ms_per_step"] / out["vdb"]["ms_per_step"]
     return out
