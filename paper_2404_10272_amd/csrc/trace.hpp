@@ -668,9 +668,10 @@ __device__ __forceinline__ void trace_ray(const GridView &g, const Tree &tree, c
 
 // ------------------------------------------------------------------ expansion fill
 
-// Expansion fill: a block takes 256 consecutive rays and writes their output
-// range [offsets[r0], offsets[r0 + 256]) with consecutive lanes on consecutive
-// 4-output groups (full-wave 16-byte stores).  The rays' kept runs are staged
+// Expansion fill: the output range [offsets[r0], offsets[r0 + 256]) of 256
+// consecutive rays (a chunk) is cut into windows of 4-output groups, and a
+// block writes its share of them with consecutive lanes on consecutive groups
+// (full-wave 16-byte stores).  The rays' kept runs are staged
 // in LDS in output order with block-relative first outputs; a ray whose runs
 // were lost contributes one placeholder run over its outputs, which the
 // traversal fill writes instead, so the runs tile the outputs without gaps.
