@@ -1,6 +1,7 @@
-"""The Python example of the README runs as written and gives what it says:
-one ray through a solid 50^3 block of a 128^3 grid, its samples on the
-5e-3 lattice inside the block, a differentiable composite and a refresh."""
+"""The Python example of the README runs as written: one ray through a solid
+50^3 block of a 128^3 grid gives exactly the lattice points inside the block
+(worked out in binary32 from the block's dyadic planes), the composite
+differentiates, and a refresh with the same occupancy changes nothing."""
 import numpy as np
 import pytest
 import torch
@@ -20,10 +21,18 @@ def test_readme_example():
     out = api.sample_rays(grid, o, d, near=2.0, far=6.0, step=api.make_step("const", dt=5e-3))
     t0 = out["t0"].cpu().numpy()
     S = int(out["offsets"][-1].item())
-    # the block spans z in [-1.5 + 40*3/128, -1.5 + 90*3/128) = [-0.5625, 0.6094), i.e. t in (3.4375, 4.6094]
-    assert S == t0.size and 200 <= S <= 240
-    assert t0.min() > 3.43 and out["t1"].cpu().numpy().max() < 4.62
-    assert np.all(np.diff(t0) > 0) and np.all(out["ray_ids"].cpu().numpy() == 0)
+    # The block's planes z = -1.5 + m*3/128 (m = 40, 90) are dyadic, so the ray
+    # (o_z = -4, d_z = 1) crosses them exactly at t = 3.4375 and 4.609375, and
+    # the samples are the lattice points t_n = fl(2 + fl(n * 5e-3)) in that
+    # interval (upper end included), in binary32.
+    dt = np.float32(5e-3)
+    n = np.arange(1000, dtype=np.float32)
+    lat = np.float32(2.0) + n * dt
+    sel = n[(lat > np.float32(3.4375)) & (lat <= np.float32(4.609375))]
+    assert S == sel.size == 234
+    np.testing.assert_array_equal(t0, np.float32(2.0) + sel * dt)
+    np.testing.assert_array_equal(out["t1"].cpu().numpy(), np.float32(2.0) + (sel + np.float32(1.0)) * dt)
+    assert np.all(out["ray_ids"].cpu().numpy() == 0)
     sigma = torch.rand(S, device="cuda", requires_grad=True)
     rgb = torch.rand(S, 3, device="cuda", requires_grad=True)
     C, A = api.composite(sigma, rgb, out["offsets"], out["t0"], out["t1"])
