@@ -72,25 +72,18 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kGr
     add_tile_sums(i, n, tile_sums);
 }
 
-// Traversal fill: re-walks rays and writes their samples from offsets[i]:
-// every ray (list == nullptr; used when voxel ids are requested), or the
-// *list_len rays of `list` (the rays whose runs the count pass could not
-// keep), over a grid that strides through the list.
+// Traversal fill: re-walks every ray and writes its samples from offsets[i]
+// (used when voxel ids are requested; the expansion fill writes the rest).
 template <int kGrid, bool kSkip, bool kVox, bool kLds>
 __global__ void __launch_bounds__(kBlock) fill_kernel(GridView g, const float *__restrict__ origins,
                                                       const float *__restrict__ dirs, int64_t n_rays, Lattice lat,
                                                       const int64_t *__restrict__ offsets, int64_t capacity,
                                                       int32_t *__restrict__ ray_ids, float *__restrict__ t0,
-                                                      float *__restrict__ t1, int32_t *__restrict__ vox,
-                                                      const int32_t *__restrict__ list,
-                                                      const int32_t *__restrict__ list_len) {
+                                                      float *__restrict__ t1, int32_t *__restrict__ vox) {
     extern __shared__ uint32_t smem[];
-    const int64_t m = list ? (int64_t)*list_len : n_rays;
-    if ((int64_t)blockIdx.x * kBlock >= m) return;   // block-uniform: no work, skip the staging too
     Tree tree = kGrid == 1 ? load_tree<kLds>(g, smem) : Tree{};
     const FillCtx ctx{lat, capacity, ray_ids, t0, t1, vox, g.R};
-    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < m; k += (int64_t)gridDim.x * kBlock) {
-        const int64_t i = list ? (int64_t)list[k] : k;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n_rays; i += (int64_t)gridDim.x * kBlock) {
         const int64_t first = offsets[i];
         if (first >= capacity) continue;
         float o[3], d[3];
@@ -402,22 +395,17 @@ void launch_count(const GridView &g, const float *o, const float *d, int64_t n, 
             <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool, width, b.tiles);
 }
 
-// Lost-ray fills run on a small grid that strides through the list.
-constexpr unsigned kListBlocks = 64;
-
 template <int kGrid, bool kSkip, bool kLds>
 void launch_fill(const GridView &g, const float *o, const float *d, int64_t n, const Lattice &lat,
                  const int64_t *offsets, int64_t cap, int32_t *ids, float *t0, float *t1, int32_t *vox,
-                 const int32_t *list, const int32_t *list_len, hipStream_t s) {
-    unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
-    if (list) blocks = std::min(blocks, kListBlocks);
-    size_t shm = kLds ? lds_bytes(g) : 0;
+                 hipStream_t s) {
+    const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
+    const size_t shm = kLds ? lds_bytes(g) : 0;
     if (vox)
-        fill_kernel<kGrid, kSkip, true, kLds>
-            <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, offsets, cap, ids, t0, t1, vox, list, list_len);
+        fill_kernel<kGrid, kSkip, true, kLds><<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, offsets, cap, ids, t0, t1, vox);
     else
-        fill_kernel<kGrid, kSkip, false, kLds>
-            <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, offsets, cap, ids, t0, t1, vox, list, list_len);
+        fill_kernel<kGrid, kSkip, false, kLds><<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, offsets, cap, ids, t0, t1,
+                                                                          vox);
 }
 
 void dispatch_count(const GridView &g, int variant, const float *o, const float *d, int64_t n, const Lattice &lat,
@@ -440,9 +428,9 @@ void dispatch_count(const GridView &g, int variant, const float *o, const float 
 
 void dispatch_fill(const GridView &g, int variant, const float *o, const float *d, int64_t n, const Lattice &lat,
                    const int64_t *offsets, int64_t cap, int32_t *ids, float *t0, float *t1, int32_t *vox,
-                   const int32_t *list, const int32_t *list_len, hipStream_t s) {
+                   hipStream_t s) {
     const bool lds = lds_bytes(g) <= kLdsTreeBytes;
-#define OGV_FILL(V, K, L) launch_fill<V, K, L>(g, o, d, n, lat, offsets, cap, ids, t0, t1, vox, list, list_len, s)
+#define OGV_FILL(V, K, L) launch_fill<V, K, L>(g, o, d, n, lat, offsets, cap, ids, t0, t1, vox, s)
     if (g.kind == 0) {
         if (variant == OGV_SKIP) OGV_FILL(0, true, false);
         else OGV_FILL(0, false, false);
@@ -494,7 +482,7 @@ ogv_status fill_all(const ogv_grid *grid, int32_t variant, const float *o, const
     if (n == 0 || cap == 0) return OGV_OK;
     Bufs b = bufs_of(ws, p);
     if (vox) {
-        dispatch_fill(grid->view, variant, o, d, n, lat, offsets, cap, ids, t0, t1, vox, nullptr, nullptr, s);
+        dispatch_fill(grid->view, variant, o, d, n, lat, offsets, cap, ids, t0, t1, vox, s);
         OGV_CHECK_LAUNCH();
         return OGV_OK;
     }

@@ -26,14 +26,6 @@ def packed():
     return out, sigma, rgb, target
 
 
-def _per_ray_close(got, ref, offsets_or_none=None):
-    got = np.asarray(got, np.float64)
-    ref = np.asarray(ref, np.float64)
-    scale = np.maximum(np.abs(ref).max(axis=tuple(range(1, ref.ndim))) if ref.ndim > 1 else np.abs(ref), 1e-30)
-    err = np.abs(got - ref).max(axis=tuple(range(1, ref.ndim))) if ref.ndim > 1 else np.abs(got - ref)
-    return err, scale
-
-
 def test_forward_backward_against_oracle(packed):
     out, sigma, rgb, target = packed
     offsets = out["offsets"]
