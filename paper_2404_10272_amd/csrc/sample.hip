@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kGr
                                                        int32_t *__restrict__ counts, int32_t *__restrict__ nruns,
                                                        RunPool pool, int image_width,
                                                        int64_t *__restrict__ tile_sums) {
-    extern __shared__ uint32_t smem[];
+    extern __shared__ __align__(16) uint32_t smem[];
     Tree tree = kGrid == 1 ? load_tree<kLds>(g, smem) : Tree{};
     const int64_t i = ray_of_thread((int64_t)blockIdx.x * kBlock + threadIdx.x, n_rays, image_width);
     int32_t n = 0;
@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(kBlock) fill_kernel(GridView g, const float *_
                                                       const int64_t *__restrict__ offsets, int64_t capacity,
                                                       int32_t *__restrict__ ray_ids, float *__restrict__ t0,
                                                       float *__restrict__ t1, int32_t *__restrict__ vox) {
-    extern __shared__ uint32_t smem[];
+    extern __shared__ __align__(16) uint32_t smem[];
     Tree tree = kGrid == 1 ? load_tree<kLds>(g, smem) : Tree{};
     const FillCtx ctx{lat, capacity, ray_ids, t0, t1, vox, g.R};
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n_rays; i += (int64_t)gridDim.x * kBlock) {

@@ -79,7 +79,26 @@ __host__ __device__ inline size_t tree_lds_bytes(int L, int NR, int S) {
     return n_root * 4 + n_root * (size_t)S * S * S * 4;
 }
 
-// Every thread of the block must call this (it synchronizes).
+// Copies n4 >= 1 16-byte words from global memory to LDS.  A thread issues
+// the loads of a batch together and only then stores them, so the block waits
+// for one memory round trip per batch rather than one per word.  Indices past
+// the end are clamped to the last word, which such lanes load and store again
+// with its own value: no branch lets the compiler sink a load to its store.
+__device__ __forceinline__ void stage_to_lds(int4 *dst, const int4 *__restrict__ src, int n4) {
+    constexpr int kBatch = 4;
+    const int nt = (int)blockDim.x, t = (int)threadIdx.x;
+    for (int base = 0; base < n4; base += kBatch * nt) {
+        int4 r[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) r[u] = src[min(base + u * nt + t, n4 - 1)];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) dst[min(base + u * nt + t, n4 - 1)] = r[u];
+    }
+}
+
+// Every thread of the block must call this (it synchronizes).  smem must be
+// 16-byte aligned; the slot table is (the build aligns every table to 256
+// bytes, and a table holds S^3 entries per root cell, a multiple of 4).
 template <bool kLds>
 __device__ __forceinline__ Tree load_tree(const GridView &g, uint32_t *smem) {
     Tree t;
@@ -97,7 +116,7 @@ __device__ __forceinline__ Tree load_tree(const GridView &g, uint32_t *smem) {
     const int ns = n_root * g.S * g.S * g.S;
     int32_t *slot = (int32_t *)smem;
     int32_t *root = slot + ns;
-    for (int i = threadIdx.x; i < ns; i += blockDim.x) slot[i] = g.slot[i];
+    stage_to_lds(reinterpret_cast<int4 *>(slot), reinterpret_cast<const int4 *>(g.slot), ns >> 2);
     for (int i = threadIdx.x; i < n_root; i += blockDim.x) root[i] = g.root[i];
     __syncthreads();
     t.root = root;
