@@ -316,7 +316,11 @@ def main():
         plain_rows = Timed(api, torch, dense, w, o, d, "branch", 0)
         distg = api.build_dist(occ, w.boxes)
         chess = Timed(api, torch, distg, w, o, d, "branch", W)
-        assert hdda.S == plain.S == hdda_other.S == plain_skip.S == chess.S, "samplers disagree on the sample count"
+        # the same tree walked one voxel per step ("VDB + DDA", Tab. 1-2)
+        vox = Timed(api, torch, vdb, w, o, d, "voxel_" + args.variant, W)
+        vox_other = Timed(api, torch, vdb, w, o, d, "voxel_" + other, W)
+        assert hdda.S == plain.S == hdda_other.S == plain_skip.S == chess.S == vox.S == vox_other.S, \
+            "samplers disagree on the sample count"
         N_ = w.n_rays
 
         def rec(t):
@@ -332,6 +336,8 @@ def main():
         compare["dense_row_major_lanes"] = rec(plain_rows)
         # dense bitfield + capped chessboard distances (skips the empty cube around an empty voxel)
         compare["chessboard"] = dict(rec(chess), bytes=distg.info()["bytes"])
+        compare["vdb_voxel_steps"] = rec(vox)
+        compare["vdb_voxel_steps_" + other] = rec(vox_other)
         compare["speedup_vs_dense"] = compare["dense"]["ms_per_step"] / ms
     count_ms = walk_ms + scan_ms
     N, S = w.n_rays, hdda.S

@@ -62,16 +62,22 @@ typedef int32_t ogv_status;
  *                 occupancy (NerfAcc's structure);
  *   OGV_SKIP   -- Alg. 2 "DDA skip": pass over all leading empty cells, then
  *                 march the occupied run (Instant-NGP's structure).
- * Both give identical samples. */
+ * OGV_VOXEL may be or-ed into either, for VDB grids only: the tree is then
+ * walked one voxel per step, each voxel's occupancy looked up in the tree and
+ * no tile skipped in one step (the "VDB + DDA" rows of Tab. 1-2, against the
+ * default hierarchical steps of "VDB + HDDA").  A sampling call rejects it on
+ * any other grid with OGV_ERR_INVALID; batches take OGV_BRANCH or OGV_SKIP
+ * only.  Every variant gives identical samples. */
 #define OGV_BRANCH 0
 #define OGV_SKIP 1
+#define OGV_VOXEL 2
 
 /* Options of a sampling call (NULL means {OGV_BRANCH, 0}).  image_width > 0
  * says the rays are the row-major pixels of an image that wide; lanes then
  * take 8x8 pixel tiles so neighbouring rays walk together.  It changes only
  * speed, never the samples or their order. */
 typedef struct {
-    int32_t variant;      /* OGV_BRANCH or OGV_SKIP */
+    int32_t variant;      /* OGV_BRANCH or OGV_SKIP, optionally | OGV_VOXEL */
     int32_t image_width;  /* >= 0 */
 } ogv_sample_opts;
 

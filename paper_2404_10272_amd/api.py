@@ -13,7 +13,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libogvdb.so")
 
-BRANCH, SKIP = 0, 1
+BRANCH, SKIP, VOXEL = 0, 1, 2
 STEP_CONST, STEP_CONE = 0, 1
 
 
@@ -135,7 +135,14 @@ def make_step(kind="const", dt=0.0, cone=0.0, dt_min=0.0):
 
 
 def _variant(v):
-    return {"branch": BRANCH, "skip": SKIP, BRANCH: BRANCH, SKIP: SKIP}[v]
+    """Loop variant: "branch", "skip", "voxel_branch", "voxel_skip" (VDB grids
+    walked one voxel per step) or the ogvdb.h value."""
+    names = {"branch": BRANCH, "skip": SKIP, "voxel_branch": BRANCH | VOXEL, "voxel_skip": SKIP | VOXEL}
+    if isinstance(v, str):
+        return names[v]
+    if v not in names.values():
+        raise ValueError(f"unknown variant {v!r}")
+    return int(v)
 
 
 class Grid:

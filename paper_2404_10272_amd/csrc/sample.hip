@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kGr
                                                        RunPool pool, int image_width,
                                                        int64_t *__restrict__ tile_sums) {
     extern __shared__ __align__(16) uint32_t smem[];
-    Tree tree = kGrid == 1 ? load_tree<kLds>(g, smem) : Tree{};
+    Tree tree = reads_tree(kGrid) ? load_tree<kLds>(g, smem) : Tree{};
     const int64_t i = ray_of_thread((int64_t)blockIdx.x * kBlock + threadIdx.x, n_rays, image_width);
     int32_t n = 0;
     if (i >= 0) {
@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(kBlock) fill_kernel(GridView g, const float *_
                                                       int32_t *__restrict__ ray_ids, float *__restrict__ t0,
                                                       float *__restrict__ t1, int32_t *__restrict__ vox) {
     extern __shared__ __align__(16) uint32_t smem[];
-    Tree tree = kGrid == 1 ? load_tree<kLds>(g, smem) : Tree{};
+    Tree tree = reads_tree(kGrid) ? load_tree<kLds>(g, smem) : Tree{};
     const FillCtx ctx{lat, capacity, ray_ids, t0, t1, vox, g.R};
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n_rays; i += (int64_t)gridDim.x * kBlock) {
         const int64_t first = offsets[i];
@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kEx
     expand_block(offsets, n_rays, nruns, rd, OneLattice{lat}, capacity, ray_ids, t0, t1, vec4 != 0);
     const int64_t m = *n_lost;
     if (m == 0) return;
-    const Tree tree = kGrid == 1 ? load_tree<false>(g, nullptr) : Tree{};
+    const Tree tree = reads_tree(kGrid) ? load_tree<false>(g, nullptr) : Tree{};
     const FillCtx ctx{lat, capacity, ray_ids, t0, t1, nullptr, g.R};
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < m; k += (int64_t)gridDim.x * kBlock) {
         const int64_t i = lost[k];
@@ -268,7 +268,9 @@ ogv_status validate_sampling(const ogv_grid *grid, int32_t variant, const float 
                     float near_t, float far_t, const ogv_step *step, const char *fn) {
     std::string f(fn);
     if (!grid) OGV_FAIL(OGV_ERR_INVALID, f + ": grid is null");
-    if (variant != OGV_BRANCH && variant != OGV_SKIP) OGV_FAIL(OGV_ERR_INVALID, f + ": variant must be 0 or 1");
+    if (variant < 0 || variant > (OGV_SKIP | OGV_VOXEL)) OGV_FAIL(OGV_ERR_INVALID, f + ": variant must be 0..3");
+    if ((variant & OGV_VOXEL) && grid->view.kind != 1)
+        OGV_FAIL(OGV_ERR_INVALID, f + ": OGV_VOXEL walks a VDB grid; this grid is not one");
     if (n_rays < 0 || n_rays > (int64_t)INT32_MAX) OGV_FAIL(OGV_ERR_INVALID, f + ": n_rays out of range");
     if (n_rays > 0 && (!o || !d)) OGV_FAIL(OGV_ERR_INVALID, f + ": null ray pointer");
     if (!step) OGV_FAIL(OGV_ERR_INVALID, f + ": step is null");
@@ -408,43 +410,52 @@ void launch_fill(const GridView &g, const float *o, const float *d, int64_t n, c
                                                                           vox);
 }
 
+// Traversal of a call (the CursorOf index): the grid's kind, or 3 for a VDB
+// grid walked one voxel per step.
+int traversal_of(const GridView &g, int variant) { return (variant & OGV_VOXEL) ? 3 : g.kind; }
+
+// Calls OGV_LAUNCH(traversal, skip, tree in LDS) with the instantiation that
+// serves (g, variant).
+#define OGV_DISPATCH(g, variant)                                         \
+    do {                                                                 \
+        const bool sk_ = ((variant) & OGV_SKIP) != 0;                    \
+        const bool lds_ = lds_bytes(g) <= kLdsTreeBytes;                 \
+        switch (traversal_of(g, variant)) {                              \
+        case 0:                                                          \
+            if (sk_) OGV_LAUNCH(0, true, false);                         \
+            else OGV_LAUNCH(0, false, false);                            \
+            break;                                                       \
+        case 2:                                                          \
+            if (sk_) OGV_LAUNCH(2, true, false);                         \
+            else OGV_LAUNCH(2, false, false);                            \
+            break;                                                       \
+        case 3:                                                          \
+            if (sk_ && lds_) OGV_LAUNCH(3, true, true);                  \
+            else if (sk_) OGV_LAUNCH(3, true, false);                    \
+            else if (lds_) OGV_LAUNCH(3, false, true);                   \
+            else OGV_LAUNCH(3, false, false);                            \
+            break;                                                       \
+        default:                                                         \
+            if (sk_ && lds_) OGV_LAUNCH(1, true, true);                  \
+            else if (sk_) OGV_LAUNCH(1, true, false);                    \
+            else if (lds_) OGV_LAUNCH(1, false, true);                   \
+            else OGV_LAUNCH(1, false, false);                            \
+        }                                                                \
+    } while (0)
+
 void dispatch_count(const GridView &g, int variant, const float *o, const float *d, int64_t n, const Lattice &lat,
                     const Bufs &b, int width, hipStream_t s) {
-    const bool lds = lds_bytes(g) <= kLdsTreeBytes;
-    if (g.kind == 0) {
-        if (variant == OGV_SKIP) launch_count<0, true, false>(g, o, d, n, lat, b, width, s);
-        else launch_count<0, false, false>(g, o, d, n, lat, b, width, s);
-    } else if (g.kind == 2) {
-        if (variant == OGV_SKIP) launch_count<2, true, false>(g, o, d, n, lat, b, width, s);
-        else launch_count<2, false, false>(g, o, d, n, lat, b, width, s);
-    } else if (lds) {
-        if (variant == OGV_SKIP) launch_count<1, true, true>(g, o, d, n, lat, b, width, s);
-        else launch_count<1, false, true>(g, o, d, n, lat, b, width, s);
-    } else {
-        if (variant == OGV_SKIP) launch_count<1, true, false>(g, o, d, n, lat, b, width, s);
-        else launch_count<1, false, false>(g, o, d, n, lat, b, width, s);
-    }
+#define OGV_LAUNCH(V, K, L) launch_count<V, K, (V == 1 || V == 3) && L>(g, o, d, n, lat, b, width, s)
+    OGV_DISPATCH(g, variant);
+#undef OGV_LAUNCH
 }
 
 void dispatch_fill(const GridView &g, int variant, const float *o, const float *d, int64_t n, const Lattice &lat,
                    const int64_t *offsets, int64_t cap, int32_t *ids, float *t0, float *t1, int32_t *vox,
                    hipStream_t s) {
-    const bool lds = lds_bytes(g) <= kLdsTreeBytes;
-#define OGV_FILL(V, K, L) launch_fill<V, K, L>(g, o, d, n, lat, offsets, cap, ids, t0, t1, vox, s)
-    if (g.kind == 0) {
-        if (variant == OGV_SKIP) OGV_FILL(0, true, false);
-        else OGV_FILL(0, false, false);
-    } else if (g.kind == 2) {
-        if (variant == OGV_SKIP) OGV_FILL(2, true, false);
-        else OGV_FILL(2, false, false);
-    } else if (lds) {
-        if (variant == OGV_SKIP) OGV_FILL(1, true, true);
-        else OGV_FILL(1, false, true);
-    } else {
-        if (variant == OGV_SKIP) OGV_FILL(1, true, false);
-        else OGV_FILL(1, false, false);
-    }
-#undef OGV_FILL
+#define OGV_LAUNCH(V, K, L) launch_fill<V, K, (V == 1 || V == 3) && L>(g, o, d, n, lat, offsets, cap, ids, t0, t1, vox, s)
+    OGV_DISPATCH(g, variant);
+#undef OGV_LAUNCH
 }
 
 ogv_status build_table(float near_t, float far_t, const ogv_step *step, void *ws, const Plan &p, hipStream_t s) {
@@ -489,20 +500,13 @@ ogv_status fill_all(const ogv_grid *grid, int32_t variant, const float *o, const
     const unsigned blocks = (unsigned)min(expand_items(n), (int64_t)INT32_MAX);
     const int vec4 = (((uintptr_t)ids | (uintptr_t)t0 | (uintptr_t)t1) & 15) == 0;
     const GridView &g = grid->view;
-#define OGV_EXPAND(V, K)                                                                                            \
+    // the expansion's lost-ray walk reads the tree from global memory (the
+    // LDS flag is ignored)
+#define OGV_LAUNCH(V, K, L)                                                                                          \
     expand_kernel<V, K><<<blocks, kBlock, 0, s>>>(g, o, d, offsets, n, b.nruns, reader_of(b), lat, cap, ids, t0, t1, \
                                                    vec4, b.pool.lost, b.pool.n_lost)
-    if (g.kind == 0) {
-        if (variant == OGV_SKIP) OGV_EXPAND(0, true);
-        else OGV_EXPAND(0, false);
-    } else if (g.kind == 2) {
-        if (variant == OGV_SKIP) OGV_EXPAND(2, true);
-        else OGV_EXPAND(2, false);
-    } else {
-        if (variant == OGV_SKIP) OGV_EXPAND(1, true);
-        else OGV_EXPAND(1, false);
-    }
-#undef OGV_EXPAND
+    OGV_DISPATCH(g, variant);
+#undef OGV_LAUNCH
     OGV_CHECK_LAUNCH();
     return OGV_OK;
 }

@@ -137,7 +137,13 @@ __device__ __forceinline__ Tree load_tree(const GridView &g, uint32_t *smem) {
 // the walk descends into a finer cell; a change of size recomputes all three
 // exits.  Cell sequence and exit parameters equal those of a walk that
 // re-locates every axis at every exit.
-struct VdbCursor {
+//
+// kTiles = false walks the same tree one voxel per step (the paper's
+// "VDB + DDA" rows, Tab. 1-2): a voxel inside a tile takes the tile's value
+// and the walk moves on to the next voxel, so the tree only changes how
+// occupancy is looked up, not which cells are visited.
+template <bool kTiles>
+struct VdbWalk {
     Tree t;
     int lev, R, sh;
     Axis A0, A1, A2;
@@ -176,7 +182,7 @@ struct VdbCursor {
                 wx = -1;
             } else {
                 o = root_tile ? node == -2 : c == -2;
-                return root_tile ? (8 << t.ilog2) : 8;
+                return kTiles ? (root_tile ? (8 << t.ilog2) : 8) : 1;
             }
         }
         if ((v0 & 7) != wx) {
@@ -541,20 +547,28 @@ struct Ray {
     float o0, o1, o2, d0, d1, d2, r0, r1, r2;
 };
 
-// Grid kinds: 0 dense bitfield, 1 VDB tree, 2 dense bitfield with chessboard
-// distances (GridView::kind).
+// Traversals: 0 dense bitfield, 1 VDB tree with hierarchical steps, 2 dense
+// bitfield with chessboard distances (GridView::kind 0, 1, 2), and 3 the VDB
+// tree walked one voxel per step (a kind-1 grid).
 template <int kGrid>
 struct CursorOf {
     using type = DenseCursor;
 };
 template <>
 struct CursorOf<1> {
-    using type = VdbCursor;
+    using type = VdbWalk<true>;
 };
 template <>
 struct CursorOf<2> {
     using type = DistCursor;
 };
+template <>
+struct CursorOf<3> {
+    using type = VdbWalk<false>;
+};
+
+// Traversals that read the VDB tree.
+constexpr bool reads_tree(int kGrid) { return kGrid == 1 || kGrid == 3; }
 
 // Puts the cursor of level `lev` on the voxel owning t_min when t_min lies
 // after the segment start a, else on the voxel owning the parameters just

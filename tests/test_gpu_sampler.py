@@ -16,8 +16,8 @@ from tests import handmade
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [("dense", "branch"), ("dense", "skip"), ("vdb", "branch"), ("vdb", "skip"), ("dist", "branch"),
-            ("dist", "skip")]
+VARIANTS = [("dense", "branch"), ("dense", "skip"), ("vdb", "branch"), ("vdb", "skip"), ("vdb", "voxel_branch"),
+            ("vdb", "voxel_skip"), ("dist", "branch"), ("dist", "skip")]
 _VID = lambda v: f"{v[0]}-{v[1]}"
 
 
@@ -280,6 +280,24 @@ def test_invalid_arguments_raise(small):
         api.sample_rays(g, o, o, 2.0, 6.0, api.make_step("const", dt=0.0))
     with pytest.raises(api.OgvError):
         api.build_vdb(torch.zeros((8, 8, 8), dtype=torch.uint8, device="cuda"), [0, 0, 0, 1, 1, 1], internal_log2=9)
+
+
+def test_voxel_steps_only_on_vdb_grids(small):
+    """OGV_VOXEL names a way to walk a VDB tree: a dense or distance grid
+    rejects it, and an undefined variant bit is rejected on every grid."""
+    o = torch.from_numpy(small.origins[:64]).cuda()
+    d = torch.from_numpy(small.dirs[:64]).cuda()
+    step = api.make_step(small.step)
+    for kind in ("dense", "dist"):
+        g = gpu_grid(kind, small.occ, small.boxes, small.ilog2)
+        for v in ("voxel_branch", "voxel_skip"):
+            with pytest.raises(api.OgvError):
+                api.sample_rays(g, o, d, small.near, small.far, step, v)
+    g = gpu_grid("vdb", small.occ, small.boxes, small.ilog2)
+    sp = api.Sampler(g, 64, small.near, small.far, step)
+    sp.opts.variant = 4
+    with pytest.raises(api.OgvError):
+        sp.count(o, d)
 
 
 def test_determinism(obj):
