@@ -156,14 +156,13 @@ struct VdbWalk {
     bool occ;              // current cell occupied
     int lblk;              // cached leaf block (packed block coordinates), -1 if none
     int lbase;             // its first word in the leaf array
-    int wx;                // cached word: voxel x within the leaf (-1: none)
-    uint64_t word;
 
     // Size of the largest uniform cell holding voxel (v0, v1, v2) and its
-    // occupancy; for a voxel inside a leaf the leaf and word are cached.  A
-    // voxel in the cached leaf block (most voxel steps) needs only the word
-    // and bit; otherwise the root and slot tables are read and a leaf found
-    // there becomes the cached one.
+    // occupancy.  A voxel in the cached leaf block (most voxel steps) needs
+    // only its word and bit; otherwise the root and slot tables are read and
+    // a leaf found there becomes the cached one.  The word is read on every
+    // leaf voxel: keeping the last one costs a divergent branch per step,
+    // which is dearer than the (cached) load.
     __device__ __forceinline__ int classify(bool &o) {
         const int blk = ((v0 >> 3) << 20) | ((v1 >> 3) << 10) | (v2 >> 3);
         int D = 1;
@@ -179,16 +178,12 @@ struct VdbWalk {
             if (!root_tile && !slot_tile) {
                 lblk = blk;
                 lbase = c * 8;
-                wx = -1;
             } else {
                 o = root_tile ? node == -2 : c == -2;
                 return kTiles ? (root_tile ? (8 << t.ilog2) : 8) : 1;
             }
         }
-        if ((v0 & 7) != wx) {
-            wx = v0 & 7;
-            word = t.leaves[lbase + wx];
-        }
+        const uint64_t word = t.leaves[lbase + (v0 & 7)];
         const int bit = ((v1 & 7) << 3) | (v2 & 7);
         const uint32_t half = bit < 32 ? (uint32_t)word : (uint32_t)(word >> 32);
         o = ((half >> (bit & 31)) & 1u) != 0;
@@ -614,8 +609,6 @@ __device__ __forceinline__ bool cursor_begin(typename CursorOf<kGrid>::type &c, 
         c.k0 = c.k1 = c.k2 = 0;
         c.lblk = -1;
         c.lbase = 0;
-        c.wx = -1;
-        c.word = 0;
         c.enter();
     }
     return true;
