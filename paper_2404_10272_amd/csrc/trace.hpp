@@ -190,26 +190,19 @@ struct VdbWalk {
         return D;
     }
 
-    // exit planes and parameters of every moving axis for cells of size D
+    // exit planes and parameters of every moving axis for cells of size D.
+    // Every axis is computed and a zero axis's parameter replaced by +inf
+    // afterwards: a per-axis branch here costs more than the arithmetic.
     __device__ __forceinline__ void exits_all() {
         const float inf = __builtin_huge_valf();
         const int msk = ~(D - 1);
-        e0 = e1 = e2 = inf;
-        if (!A0.zero) {
-            const int b = v0 & msk;
-            k0 = A0.pos ? b + D : R - b;
-            e0 = A0.Tk(k0);
-        }
-        if (!A1.zero) {
-            const int b = v1 & msk;
-            k1 = A1.pos ? b + D : R - b;
-            e1 = A1.Tk(k1);
-        }
-        if (!A2.zero) {
-            const int b = v2 & msk;
-            k2 = A2.pos ? b + D : R - b;
-            e2 = A2.Tk(k2);
-        }
+        const int b0 = v0 & msk, b1 = v1 & msk, b2 = v2 & msk;
+        k0 = A0.pos ? b0 + D : R - b0;
+        k1 = A1.pos ? b1 + D : R - b1;
+        k2 = A2.pos ? b2 + D : R - b2;
+        e0 = A0.zero ? inf : A0.Tk(k0);
+        e1 = A1.zero ? inf : A1.Tk(k1);
+        e2 = A2.zero ? inf : A2.Tk(k2);
     }
 
     // the cell holding the current voxels becomes current
@@ -489,12 +482,16 @@ struct DistCursor {
         occ = d == 0;
         h = d >= 2 ? d - 1 : 0;
     }
+    // every axis computed, a zero axis's parameter replaced by +inf (cheaper
+    // than a per-axis branch)
     __device__ __forceinline__ void exits_all() {
         const float inf = __builtin_huge_valf();
-        e0 = e1 = e2 = inf;
-        if (!A0.zero) { k0 = min(u0 + h + 1, R); e0 = A0.Tk(k0); }
-        if (!A1.zero) { k1 = min(u1 + h + 1, R); e1 = A1.Tk(k1); }
-        if (!A2.zero) { k2 = min(u2 + h + 1, R); e2 = A2.Tk(k2); }
+        k0 = min(u0 + h + 1, R);
+        k1 = min(u1 + h + 1, R);
+        k2 = min(u2 + h + 1, R);
+        e0 = A0.zero ? inf : A0.Tk(k0);
+        e1 = A1.zero ? inf : A1.Tk(k1);
+        e2 = A2.zero ? inf : A2.Tk(k2);
     }
     __device__ __forceinline__ void enter() {
         classify();
