@@ -71,6 +71,14 @@ def test_batch_matches_oracle_reduced(kind):
         _same(_split(res, base, w.n_rays, s), ref, f"scene {s}")
 
 
+def test_batch_rejects_voxel_steps():
+    # a batch walks each VDB hierarchically; OGV_VOXEL is a single-scene option
+    ws = scenes.batched(n_scenes=2, ray_sides=[64, 64])
+    for v in ("voxel_branch", "voxel_skip"):
+        with pytest.raises(api.OgvError):
+            api.Batch(_gpu_scenes(ws), v, tune=(256, 2))
+
+
 def test_graph_replays_match_eager_and_tunes_agree():
     ws = scenes.batched(ray_sides=[s // 4 for s in scenes.BATCH_SIDES])
     gs = _gpu_scenes(ws)
