@@ -7,11 +7,12 @@ samples, inputs resident in HBM.  The dense-grid DDA marcher (the plain
 method) is timed with the same protocol on the same rays.  `value` is the
 VDB sampler's rays/s.
 
-Prints one JSON line.  `roofline` is for the dominant kernel (the VDB fill
-kernel): algorithmic bytes per launch (rays and offsets read, samples
-written, tree read once) over its average duration measured with HIP events
-on the stream it runs on.  `cpu_baseline` times the CPU oracle's VDB +
-hierarchical-DDA sampler on a bounded subset of the same rays.
+Prints one JSON line.  `roofline` divides the call's algorithmic bytes
+(24 B per ray read, 8 B per offset and 12 B per sample written, the grid read
+once) by the summed durations of its kernels, measured with HIP events on the
+stream they run on, and splits both by kernel (`per_kernel`: the walk owns the
+rays and the grid, the expansion the offsets and samples).  `cpu_baseline`
+times the CPU oracle (dense DDA and VDB + hierarchical DDA) on the host cores.
 """
 import argparse
 import json
@@ -34,7 +35,7 @@ def parse():
     p.add_argument("--variant", default="branch", choices=["skip", "branch"],
                    help="loop structure of the timed VDB sampler (Alg. 1 branch / Alg. 2 skip)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    p.add_argument("--cpu-stride", type=int, default=1, help="oracle baseline uses every k-th ray")
+    p.add_argument("--cpu-stride", type=int, default=1, help="oracle baseline uses every k-th object-scene ray")
     p.add_argument("--no-side", action="store_true", help="skip the composite and batched side measurements")
     p.add_argument("--primary-only", action="store_true",
                    help="time only the headline VDB step (no variant or dense comparisons; for profiling)")
@@ -228,43 +229,76 @@ def batched_side(api, torch, scenes, steps):
             "tune": {"chunk": info["chunk"], "blocks_per_cu": info["blocks_per_cu"], "tuned": info["tuned"]}}
 
 
-def cpu_baseline(w, stride, min_s=10.0, max_s=30.0):
-    """The oracle (VDB + hierarchical DDA, Alg. 2 loop, count + fill) on the
-    host cores, over every `stride`-th ray of the workload, repeated until at
-    least min_s seconds have passed (stopping before max_s)."""
+def host_threads():
+    """Threads the oracle may use: the CPUs this process may run on, at most
+    16 (the host share that goes with one GPU of the box; more threads than
+    that share would only time-slice)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except Exception:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _median3(fn):
+    ts, out = [], None
+    for _ in range(3):
+        t = time.perf_counter()
+        out = fn()
+        ts.append(time.perf_counter() - t)
+    return sorted(ts)[1], out
+
+
+def cpu_baseline(obj_stride=1, unb_stride=2):
+    """The oracle as it stands (count + fill of every ray, OpenMP over rays),
+    timed on the host cores: the plain dense DDA (O2) and the VDB +
+    hierarchical DDA (O3), both in the Alg. 1 loop the GPU bench times, on
+    the object workload (every `obj_stride`-th ray) and the four-cascade
+    workload (every `unb_stride`-th ray), each the median of 3 runs; O3 and O2
+    on one thread over every 64th object ray; brute force (O1) on all of the
+    64x64 small workload.  `value` is O3 on the object workload."""
     import numpy as np
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
-    scene = oracle.Scene(w.occ, w.boxes)
-    sub = slice(0, None, stride)
-    o, d = np.ascontiguousarray(w.origins[sub]), np.ascontiguousarray(w.dirs[sub])
-    scene.vdb(w.ilog2)  # build outside the timed region, as on the GPU
-    n, reps, spent, samples = o.shape[0], 0, 0.0, 0
-    while spent < min_s:
-        t = time.perf_counter()
-        out = oracle.sample_rays(scene, o, d, w.near, w.far, w.step, "hdda_skip", ilog2=w.ilog2, threads=threads)
-        one = time.perf_counter() - t
-        spent += one
-        reps += 1
-        samples = int(out["offsets"][-1])
-        if spent + one > max_s:
-            break
-    # one thread on every 16th ray of that sample: the per-core rate
-    o1, d1 = np.ascontiguousarray(o[::16]), np.ascontiguousarray(d[::16])
-    t = time.perf_counter()
-    oracle.sample_rays(scene, o1, d1, w.near, w.far, w.step, "hdda_skip", ilog2=w.ilog2, threads=1)
-    one_s = time.perf_counter() - t
+    from paper_2404_10272_amd import scenes
+    threads = host_threads()
+    methods = {}
+    spent = 0.0
+
+    def leg(name, w, stride, method, nthreads):
+        nonlocal spent
+        scene = oracle.Scene(w.occ, w.boxes)
+        if method.startswith("hdda"):
+            scene.vdb(w.ilog2)   # built outside the timed region, as on the GPU
+        o = np.ascontiguousarray(w.origins[::stride])
+        d = np.ascontiguousarray(w.dirs[::stride])
+        run = lambda: oracle.sample_rays(scene, o, d, w.near, w.far, w.step, method, ilog2=w.ilog2,
+                                         threads=nthreads)
+        med, out = _median3(run)
+        spent += 3 * med
+        methods[name] = {"value": o.shape[0] / med, "unit": "rays/s", "median_s": med, "rays": int(o.shape[0]),
+                         "samples": int(out["offsets"][-1]), "threads": nthreads, "method": method,
+                         "sample": f"{w.name} workload, every {stride}th ray"}
+
+    obj = scenes.workload("object")
+    leg("object_hdda", obj, obj_stride, "hdda_branch", threads)
+    leg("object_dense_dda", obj, obj_stride, "dense_branch", threads)
+    leg("object_hdda_1thread", obj, 64 * obj_stride, "hdda_branch", 1)
+    leg("object_dense_dda_1thread", obj, 64 * obj_stride, "dense_branch", 1)
+    unb = scenes.workload("unbounded")
+    leg("unbounded_hdda", unb, unb_stride, "hdda_branch", threads)
+    leg("unbounded_dense_dda", unb, unb_stride, "dense_branch", threads)
+    leg("small_brute_force", scenes.workload("small"), 1, "brute", threads)
     model = ""
     try:
         model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
     except Exception:
         pass
-    return {"value": reps * n / spent, "unit": "rays/s", "cores": threads, "kind": "oracle",
-            "sample": f"every {stride}th ray of the workload ({n} rays, {samples} samples) x {reps} repeats, "
-                      f"VDB + hierarchical DDA (Alg. 2 loop), count + fill, {spent:.1f} s wall",
-            "single_thread": {"value": o1.shape[0] / one_s, "unit": "rays/s",
-                              "sample": f"every {16 * stride}th ray ({o1.shape[0]} rays), one thread, {one_s:.1f} s"},
-            "host": {"cpus": os.cpu_count(), "model": model}}
+    head = methods["object_hdda"]
+    return {"value": head["value"], "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "sample": f"object workload, every {obj_stride}th ray ({head['rays']} rays, {head['samples']} samples), "
+                      f"VDB + hierarchical DDA (Alg. 1 loop), count + fill, median of 3 runs on {threads} threads; "
+                      f"{spent:.1f} s of oracle time over all legs",
+            "methods": methods, "host": {"cpus": os.cpu_count(), "threads_allowed": threads, "model": model}}
 
 
 def main():
@@ -346,27 +380,41 @@ def main():
     # packed output, outside the timed region
     ids, t0, t1 = hdda.ids, hdda.t0, hdda.t1
     runs = int(1 + ((ids[1:] != ids[:-1]) | (t0[1:] != t1[:-1])).sum().item()) if S > 0 else 0
-    # algorithmic bytes per launch
-    walk_bytes = 24 * N + 12 * N + 8 * runs + G           # rays and grid read; counts, run counts, chain heads, runs
-    fill_bytes = 8 * N + 4 * N + 8 * runs + 12 * S        # offsets, run counts, runs read; samples written
-    step_bytes = 24 * N + 8 * (N + 1) + 12 * S + G        # the call's inputs and outputs
-    if walk_ms >= fill_ms:
-        dom = {"kernel": "count_kernel", "stage": "walk: pool reset + count_kernel (VDB, hierarchical DDA)",
-               "bytes": walk_bytes, "ms": walk_ms}
-    else:
-        dom = {"kernel": "expand_kernel", "stage": "fill: expand_kernel (kept runs, then lost rays re-walked)",
-               "bytes": fill_bytes, "ms": fill_ms}
-    achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+    # Algorithmic bytes of one call (what the method itself must move): rays
+    # read (24 B each), offsets written (8 B each), samples written (12 B
+    # each), the grid read once.  Split by kernel: the walk reads the rays and
+    # the grid, the expansion writes offsets-indexed samples (and reads the
+    # offsets); the scan moves only workspace.
+    step_bytes = 24 * N + 8 * (N + 1) + 12 * S + G
+    kern_bytes = {"count_kernel": 24 * N + G, "scan": 0, "expand_kernel": 12 * S + 8 * (N + 1)}
+    kern_ms = {"count_kernel": walk_ms, "scan": scan_ms, "expand_kernel": fill_ms}
+    # workspace traffic the two-pass design adds (not algorithmic): per-ray
+    # counts, run counts and chain heads, 8 B per kept run, the scan's reads
+    ws_bytes = {"count_kernel": 12 * N + 8 * runs, "scan": 4 * N, "expand_kernel": 4 * N + 8 * runs}
+    sum_ms = walk_ms + scan_ms + fill_ms
+    achieved = step_bytes / (sum_ms * 1e-3) / 1e9
 
-    traffic = None
+    counters = None
     tpath = os.path.join(ROOT, "profiles", "traffic_object800.json")
     if os.path.exists(tpath):
         try:
             rec = json.load(open(tpath))
             if rec.get("kernel_source_sha") == _kernel_sha():
-                traffic = rec.get("bytes_per_launch", {}).get(dom["kernel"])
+                counters = rec.get("bytes_per_launch", {})
         except Exception:
-            traffic = None
+            counters = None
+    per_kernel = {}
+    for k in kern_bytes:
+        b, t = kern_bytes[k], kern_ms[k]
+        per_kernel[k] = {"algorithmic_bytes": b, "avg_ms": t, "achieved_GBps": b / (t * 1e-3) / 1e9,
+                         "frac": b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, "workspace_bytes": ws_bytes[k]}
+        if counters is not None:
+            names = ["scan_apply_direct_kernel", "scan_reduce_kernel"] if k == "scan" else \
+                ["count_kernel", "pool_reset_kernel"] if k == "count_kernel" else [k]
+            tr = sum(counters.get(n, 0.0) for n in names)
+            per_kernel[k]["traffic"] = tr
+            per_kernel[k]["traffic_over_algorithmic"] = tr / b if b else None
+    traffic = sum(v.get("traffic", 0.0) for v in per_kernel.values()) if counters is not None else None
 
     line = {
         "metric": METRIC,
@@ -396,11 +444,13 @@ def main():
         "step_bytes": step_bytes,
         "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "runs": runs,
-        "roofline": {"bound": "hbm", "kernel": dom["kernel"], "stage": dom["stage"], "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes": dom["bytes"], "avg_ms": dom["ms"],
-                     "stages_ms": {"walk": walk_ms, "scan": scan_ms, "fill": fill_ms},
-                     "stage_bytes": {"walk": walk_bytes, "scan": 4 * N + 8 * (N + 1), "fill": fill_bytes}},
+        "roofline": {"bound": "hbm", "kernel": "sampling call: count_kernel + scan + expand_kernel",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "algorithmic_bytes": step_bytes,
+                     "algorithmic_bytes_formula": "24N + 8(N+1) + 12S + G",
+                     "avg_ms": sum_ms, "per_kernel": per_kernel,
+                     "dominant_kernel": max(kern_ms, key=kern_ms.get),
+                     "stages_ms": {"walk": walk_ms, "scan": scan_ms, "fill": fill_ms}},
     }
     line.update(compare)
     if not args.no_side:
@@ -409,7 +459,7 @@ def main():
         line["cascades"] = cascades_side(api, torch, scenes, min(args.steps, 10), 2)
         line["render"] = render_side(api, torch, scenes, hdda, w, min(args.steps, 20))
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_stride)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_stride)
     print(json.dumps(line), flush=True)
 
 

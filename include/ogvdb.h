@@ -110,8 +110,10 @@ typedef struct {
  *             nested inside the next level's (checked).
  *   occ_dev   uint8 [n_levels][res][res][res], x slowest, z fastest, nonzero
  *             = occupied; read during the call's kernels only.
- *   *out      receives the handle.  Enqueued on `stream`; the handle may be
- *             used on the same stream at once, on others after a sync. */
+ *   *out      receives the handle.  The build's kernels run on `stream`,
+ *             and the call synchronizes `stream` once before returning (the
+ *             occupancy may be freed and the handle used on any stream as
+ *             soon as the call returns). */
 ogv_status ogv_dense_build(int32_t n_levels, int32_t res, const float *boxes_host, const uint8_t *occ_dev,
                            ogv_grid **out, void *stream);
 
@@ -122,7 +124,8 @@ ogv_status ogv_dense_build(int32_t n_levels, int32_t res, const float *boxes_hos
  * paper discusses as an alternative and does not evaluate (Sec. 2.3, Fig. 1;
  * it notes the memory cost, here one byte per voxel).  Its
  * samples are the dense and VDB grids' exactly.  Batches march it by its
- * bitfield.  Same arguments and errors as ogv_dense_build. */
+ * bitfield.  Same arguments, errors and synchronization as ogv_dense_build
+ * (the call synchronizes `stream` once before returning). */
 ogv_status ogv_dist_build(int32_t n_levels, int32_t res, const float *boxes_host, const uint8_t *occ_dev,
                           ogv_grid **out, void *stream);
 
@@ -208,7 +211,8 @@ ogv_status ogv_sample_scan(int64_t n_rays, int64_t *offsets_dev, void *ws_dev, s
  *                     capacity are not written.
  *   ray_ids_dev int32 [capacity], t0_dev/t1_dev float32 [capacity].
  *   voxel_ids_dev     nullable int32 [capacity]: ((l*R+i)*R+j)*R+k of the
- *                     voxel owning t0 (debug/parity output, slower). */
+ *                     voxel owning t0 (debug/parity output, slower); needs
+ *                     n_levels * res^3 <= 2^31, else OGV_ERR_UNSUPPORTED. */
 ogv_status ogv_sample_fill(const ogv_grid *grid, const ogv_sample_opts *opts, const float *origins_dev, const float *dirs_dev,
                            int64_t n_rays, float near_t, float far_t, const ogv_step *step_host,
                            const int64_t *offsets_dev, int64_t capacity, int32_t *ray_ids_dev, float *t0_dev,

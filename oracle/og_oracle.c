@@ -210,9 +210,11 @@ static int locate(const ray_ctx *x, float t, int *lev_out, int *c)
     return 0;
 }
 
+/* Debug id ((lev*R + i)*R + j)*R + k, formed in 64 bits; callers ask for
+ * ids only on grids whose ids fit in int32 (n_levels * R^3 <= 2^31). */
 static int32_t voxel_id(int R, int lev, const int *c)
 {
-    return ((lev * R + c[0]) * R + c[1]) * R + c[2];
+    return (int32_t)((((int64_t)lev * R + c[0]) * R + c[1]) * R + c[2]);
 }
 
 static int occupied(const ray_ctx *x, int lev, const int *c)

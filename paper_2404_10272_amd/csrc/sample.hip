@@ -511,6 +511,14 @@ ogv_status fill_all(const ogv_grid *grid, int32_t variant, const float *o, const
     return OGV_OK;
 }
 
+// Voxel ids are int32: every id of the grid, ((l*R+i)*R+j)*R+k, must fit.
+ogv_status check_voxel_ids(const ogv_grid *grid, const int32_t *vox, const char *fn) {
+    const GridView &g = grid->view;
+    if (vox && (int64_t)g.L * g.R * g.R * g.R - 1 > (int64_t)INT32_MAX)
+        OGV_FAIL(OGV_ERR_UNSUPPORTED, std::string(fn) + ": voxel ids need n_levels * res^3 <= 2^31");
+    return OGV_OK;
+}
+
 ogv_status prepare(const ogv_grid *grid, const ogv_sample_opts &opts, const float *o, const float *d, int64_t n,
                    float near_t, float far_t, const ogv_step *step, void *ws, size_t ws_bytes, Plan *p,
                    const char *fn) {
@@ -603,6 +611,7 @@ extern "C" ogv_status ogv_sample_fill(const ogv_grid *grid, const ogv_sample_opt
     if (!offsets) OGV_FAIL(OGV_ERR_INVALID, "offsets is null");
     if (capacity < 0) OGV_FAIL(OGV_ERR_INVALID, "capacity < 0");
     if (capacity > 0 && (!ray_ids || !t0 || !t1)) OGV_FAIL(OGV_ERR_INVALID, "null sample array");
+    if ((st = check_voxel_ids(grid, vox, "ogv_sample_fill")) != OGV_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     Lattice lat = make_lattice(near_t, far_t, step, ws, p);
     return fill_all(grid, opts.variant, o, d, n, lat, offsets, capacity, ray_ids, t0, t1, vox, ws, p, s);
@@ -619,6 +628,7 @@ extern "C" ogv_status ogv_sample_rays(const ogv_grid *grid, const ogv_sample_opt
     if (!offsets || !overflow) OGV_FAIL(OGV_ERR_INVALID, "offsets/overflow is null");
     if (capacity < 0) OGV_FAIL(OGV_ERR_INVALID, "capacity < 0");
     if (capacity > 0 && (!ray_ids || !t0 || !t1)) OGV_FAIL(OGV_ERR_INVALID, "null sample array");
+    if ((st = check_voxel_ids(grid, vox, "ogv_sample_rays")) != OGV_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     if ((st = build_table(near_t, far_t, step, ws, p, s)) != OGV_OK) return st;
     Lattice lat = make_lattice(near_t, far_t, step, ws, p);

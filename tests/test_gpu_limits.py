@@ -87,3 +87,23 @@ def test_most_levels(kind):
                           api.make_step(step), "branch")
     torch.cuda.synchronize()
     _assert_same({k: v.cpu().numpy() for k, v in out.items()}, ref, f"8 levels {kind}")
+
+
+def test_voxel_ids_rejected_past_int32():
+    """Voxel ids are int32: on a grid with n_levels * res^3 > 2^31 (three
+    1024^3 levels) sampling works without them and a request for them is
+    rejected before any kernel runs."""
+    L, R = 3, 1024
+    occ = torch.zeros((L, R, R, R), dtype=torch.uint8, device="cuda")
+    occ[0, 500:524, 500:524, 500:524] = 1
+    boxes = np.asarray([[-2.0 ** k] * 3 + [2.0 ** k] * 3 for k in range(L)], np.float32)
+    g = api.build_dense(occ, boxes)
+    del occ
+    o = torch.tensor([[-3.0, 0.01, 0.02]], device="cuda")
+    d = torch.tensor([[1.0, 0.0, 0.0]], device="cuda")
+    step = api.make_step("const", dt=1e-3)
+    out = api.sample_rays(g, o, d, 0.0, 8.0, step)
+    torch.cuda.synchronize()
+    assert 40 <= int(out["offsets"][-1].item()) <= 50
+    with pytest.raises(api.OgvError, match="voxel ids"):
+        api.sample_rays(g, o, d, 0.0, 8.0, step, voxel_ids=True)

@@ -58,11 +58,18 @@ def test_handmade_cases(variant):
             g = gpu_grid(variant[0], occ, boxes, ilog2)
             o = np.asarray([case["o"]], np.float32)
             d = np.asarray([case["d"]], np.float32)
-            got = gpu_sample(g, o, d, case["tmin"], case["tmax"], handmade.step_of(case), variant[1])
             print(case["name"], variant, ilog2, flush=True)
-            np.testing.assert_array_equal(got["t0"], np.asarray(case["t0"], np.float32), err_msg=case["name"])
-            np.testing.assert_array_equal(got["t1"], np.asarray(case["t1"], np.float32), err_msg=case["name"])
-            np.testing.assert_array_equal(got["voxel_ids"], np.asarray(case["vox"], np.int32), err_msg=case["name"])
+            # with voxel ids (every ray re-walked by the traversal fill) and
+            # without (the runs expanded by the production fill)
+            for vox in (True, False):
+                got = gpu_sample(g, o, d, case["tmin"], case["tmax"], handmade.step_of(case), variant[1],
+                                 voxel_ids=vox)
+                what = f"{case['name']} vox={vox}"
+                np.testing.assert_array_equal(got["t0"], np.asarray(case["t0"], np.float32), err_msg=what)
+                np.testing.assert_array_equal(got["t1"], np.asarray(case["t1"], np.float32), err_msg=what)
+                np.testing.assert_array_equal(got["ray_ids"], np.zeros(len(case["t0"]), np.int32), err_msg=what)
+                if vox:
+                    np.testing.assert_array_equal(got["voxel_ids"], np.asarray(case["vox"], np.int32), err_msg=what)
 
 
 def test_handmade_vdb_structure():
@@ -137,8 +144,9 @@ def test_random_tiny_grids(seed):
                     if variant[0] == "dense" and ilog2 == 2:
                         continue
                     g = gpu_grid(variant[0], occ, boxes, ilog2)
-                    got = gpu_sample(g, o, d, tmin, tmax, step, variant[1])
-                    assert_same(got, ref, f"seed{seed} {variant} {step} {tmin},{tmax} ilog2={ilog2}")
+                    for vox in (True, False):
+                        got = gpu_sample(g, o, d, tmin, tmax, step, variant[1], voxel_ids=vox)
+                        assert_same(got, ref, f"seed{seed} {variant} {step} {tmin},{tmax} ilog2={ilog2} vox={vox}")
 
 
 # ------------------------------------------------------------------ workloads
@@ -161,8 +169,10 @@ def small_ref(small):
 @pytest.mark.parametrize("variant", VARIANTS, ids=_VID)
 def test_small_workload_all_rays(small, small_ref, variant):
     g = gpu_grid(variant[0], small.occ, small.boxes, small.ilog2)
-    got = gpu_sample(g, small.origins, small.dirs, small.near, small.far, small.step, variant[1])
-    assert_same(got, small_ref, f"small {variant}")
+    for vox, width in ((True, 0), (False, 0), (False, small.image[0])):
+        got = gpu_sample(g, small.origins, small.dirs, small.near, small.far, small.step, variant[1],
+                         voxel_ids=vox, image_width=width)
+        assert_same(got, small_ref, f"small {variant} vox={vox} width={width}")
 
 
 @pytest.fixture(scope="module")
@@ -217,13 +227,22 @@ def unb():
     return scenes.workload("unbounded")
 
 
+@pytest.fixture(scope="module")
+def unb_ref(unb):
+    return _oracle_all(unb, "dense_branch")
+
+
 @pytest.mark.parametrize("variant", VARIANTS, ids=_VID)
-def test_unbounded_cascades(unb, variant):
-    """4 nested cascades, growing step: all 1,064,960 rays."""
-    ref = _oracle_all(unb, "dense_branch")
+def test_unbounded_cascades(unb, unb_ref, variant):
+    """4 nested cascades, growing step: all 1,064,960 rays, through the
+    voxel-id traversal fill and through the production expansion (growing-step
+    lattice table), with row-major lanes and with the 8x8-pixel-tile lanes of
+    the 1280-wide image the benchmark times."""
     g = gpu_grid(variant[0], unb.occ, unb.boxes, unb.ilog2)
-    got = gpu_sample(g, unb.origins, unb.dirs, unb.near, unb.far, unb.step, variant[1], voxel_ids=True)
-    assert_same(got, ref, f"unbounded {variant}")
+    for vox, width in ((True, 0), (False, 0), (False, unb.image[0])):
+        got = gpu_sample(g, unb.origins, unb.dirs, unb.near, unb.far, unb.step, variant[1], voxel_ids=vox,
+                         image_width=width)
+        assert_same(got, unb_ref, f"unbounded {variant} vox={vox} width={width}")
 
 
 @pytest.mark.parametrize("variant", VARIANTS, ids=_VID)
