@@ -228,6 +228,25 @@ ogv_status ogv_sample_rays(const ogv_grid *grid, const ogv_sample_opts *opts, co
                            float *t1_dev, int32_t *voxel_ids_dev, int32_t *overflow_dev, void *ws_dev,
                            size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ogv_sample_rays with the workspace taken from a static per-device array of
+ * OGV_NOALLOC_SCRATCH_BYTES (64 MiB) inside the library instead of an
+ * argument.  The call allocates nothing; the caller still passes every input
+ * and output, with the meaning ogv_sample_rays gives them.  The array is
+ * reserved on each device the library runs on and held until the process
+ * ends.  A call whose workspace (ogv_sample_workspace_size) exceeds it --
+ * about 440,000 rays at a constant step -- fails with OGV_ERR_CAPACITY and
+ * does nothing.  All calls on one device share its array: calls that
+ * overlap in time on one device (other host threads, other streams) race,
+ * so the caller orders them, e.g. on one stream. */
+#define OGV_NOALLOC_SCRATCH_BYTES (64u << 20)
+ogv_status ogv_sample_rays_noalloc(const ogv_grid *grid, const ogv_sample_opts *opts, const float *origins_dev,
+                                   const float *dirs_dev, int64_t n_rays, float near_t, float far_t,
+                                   const ogv_step *step_host, int64_t *offsets_dev, int64_t capacity,
+                                   int32_t *ray_ids_dev, float *t0_dev, float *t1_dev, int32_t *voxel_ids_dev,
+                                   int32_t *overflow_dev, void *stream);
+
 /* Volume-rendering composite over packed samples (the accumulation of
  * Sec. 1; emission-absorption quadrature): per ray, dt_i = t1_i - t0_i,
  * alpha_i = 1 - exp(-sigma_i dt_i), T_i = exp(-sum_{j<i} sigma_j dt_j),

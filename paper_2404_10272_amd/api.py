@@ -84,6 +84,8 @@ SIGNATURES = {
                               VP, VP, VP, SZ, VP]),
     "ogv_sample_rays": (I32, [VP, ctypes.POINTER(_Opts), VP, VP, I64, F32, F32, ctypes.POINTER(_Step), VP, I64, VP, VP,
                               VP, VP, VP, VP, SZ, VP]),
+    "ogv_sample_rays_noalloc": (I32, [VP, ctypes.POINTER(_Opts), VP, VP, I64, F32, F32, ctypes.POINTER(_Step), VP,
+                                      I64, VP, VP, VP, VP, VP, VP]),
     "ogv_composite_fwd": (I32, [VP, I64, VP, VP, VP, VP, VP, VP, VP]),
     "ogv_composite_bwd": (I32, [VP, I64, I64, VP, VP, VP, VP, VP, VP, VP, VP, VP]),
     "ogv_render_blobs": (I32, [VP, I64, VP, VP, VP, VP, ctypes.POINTER(_BlobField), VP, VP, VP]),
@@ -321,6 +323,25 @@ def sample_rays(grid, origins, dirs, near, far, step, variant="branch", voxel_id
     if voxel_ids:
         out["voxel_ids"] = vox
     return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def sample_rays_noalloc(grid, origins, dirs, near, far, step, offsets, ray_ids, t0, t1, overflow,
+                        variant="branch", voxel_ids=None, image_width=0, stream=None):
+    """ogv_sample_rays_noalloc: count + scan + fill into caller-allocated
+    outputs (offsets int64 [N+1], ray_ids/t0/t1 of capacity len(t0),
+    overflow int32 [1]) with the library's static per-device workspace; the
+    call allocates nothing.  Returns (offsets, overflow)."""
+    o, d, n = _rays(origins, dirs)
+    st = step if isinstance(step, _Step) else make_step(step)
+    opts = _Opts(_variant(variant), int(image_width))
+    _check(lib().ogv_sample_rays_noalloc(grid.handle, ctypes.byref(opts), _ptr(o), _ptr(d), n, float(near),
+                                         float(far), ctypes.byref(st), _ptr(offsets), int(t0.numel()),
+                                         _ptr(ray_ids), _ptr(t0), _ptr(t1), _ptr(voxel_ids), _ptr(overflow),
+                                         _stream(stream)))
+    return offsets, overflow
 
 
 # ---------------------------------------------------------------- batches

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <mutex>
 #include <string>
 
 #include "geometry.hpp"
@@ -636,4 +637,61 @@ extern "C" ogv_status ogv_sample_rays(const ogv_grid *grid, const ogv_sample_opt
                              s)) != OGV_OK)
         return st;
     return fill_all(grid, opts.variant, o, d, n, lat, offsets, capacity, ray_ids, t0, t1, vox, ws, p, s);
+}
+
+// ------------------------------------------------------------------ no allocation
+
+// Workspace of ogv_sample_rays_noalloc: one file-scope array per device,
+// which the device holds until the process ends.  In host code `scratch`
+// names a host-side stand-in, not device memory: only the address
+// hipGetSymbolAddress returns for it (kept per device below) is passed to
+// kernels.  Every call on a device shares that device's copy.  Nothing in it
+// needs clearing between calls: the count pass zeroes its counters and scan
+// sums itself, every per-ray entry is written before it is read, and the
+// growing-step table is only reused when its header and hash match.
+static __device__ __align__(256) unsigned char scratch[OGV_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices];   // address of `scratch` on each device, once looked up
+
+// The current device's copy of `scratch`, looked up once per device (with
+// that device current, as it is for the caller's launches).
+ogv_status scratch_of_current_device(void **ptr) {
+    int dev = -1;
+    OGV_CHECK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) OGV_FAIL(OGV_ERR_UNSUPPORTED, "device index beyond the library's table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        OGV_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) OGV_FAIL(OGV_ERR_HIP, "hipGetSymbolAddress returned a null address for the scratch array");
+        g_scratch_dev[dev] = p;
+    }
+    *ptr = g_scratch_dev[dev];
+    return OGV_OK;
+}
+}  // namespace
+
+extern "C" ogv_status ogv_sample_rays_noalloc(const ogv_grid *grid, const ogv_sample_opts *opts_p, const float *o,
+                                              const float *d, int64_t n, float near_t, float far_t,
+                                              const ogv_step *step, int64_t *offsets, int64_t capacity,
+                                              int32_t *ray_ids, float *t0, float *t1, int32_t *vox,
+                                              int32_t *overflow, void *stream) {
+    if (!step) OGV_FAIL(OGV_ERR_INVALID, "ogv_sample_rays_noalloc: step is null");
+    if (n < 0) OGV_FAIL(OGV_ERR_INVALID, "ogv_sample_rays_noalloc: n_rays < 0");
+    Plan p;
+    std::string why;
+    if (!make_plan(n, near_t, far_t, step, &p, &why)) OGV_FAIL(OGV_ERR_UNSUPPORTED, why);
+    if (p.total > (size_t)OGV_NOALLOC_SCRATCH_BYTES)
+        OGV_FAIL(OGV_ERR_CAPACITY, "ogv_sample_rays_noalloc: the call needs " + std::to_string(p.total) +
+                                       " bytes of workspace, more than the " +
+                                       std::to_string((size_t)OGV_NOALLOC_SCRATCH_BYTES) +
+                                       "-byte static scratch; use ogv_sample_rays with a workspace");
+    void *ws = nullptr;
+    ogv_status st = scratch_of_current_device(&ws);
+    if (st != OGV_OK) return st;
+    return ogv_sample_rays(grid, opts_p, o, d, n, near_t, far_t, step, offsets, capacity, ray_ids, t0, t1, vox,
+                           overflow, ws, (size_t)OGV_NOALLOC_SCRATCH_BYTES, stream);
 }
