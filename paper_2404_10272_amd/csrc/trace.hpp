@@ -321,6 +321,13 @@ __device__ __forceinline__ void drive(Cursor &c, float a, float b, float tmax, V
 // further runs go to chunks of kMaxRuns slots taken from a shared pool and
 // chained (ray_next -> pool_next -> ...).  If the pool runs dry the ray is
 // marked kRunsLost, listed, and the traversal fill writes it instead.
+//
+// During the walk a run is only recorded, as the bits of its parameter
+// interval (lo, hi]; its lattice range is found once the walk has ended, in
+// a loop over the ray's recorded runs that also merges adjacent ranges and
+// rewrites them in place.  Lanes close runs at different steps, so doing the
+// lattice arithmetic at the close would run it, masked, in most steps of a
+// wave; after the walk the lanes of a wave do it together.
 constexpr int kMaxRuns = 16;
 constexpr int32_t kRunsLost = 0x7fffffff;
 
@@ -345,49 +352,84 @@ struct CountCtx {
 // Per-lane state of the count pass.
 struct CountVis {
     int32_t n;            // samples
-    int32_t nr;           // runs stored (kRunsLost: pool exhausted)
+    int32_t nr;           // runs recorded (kRunsLost: pool exhausted); after finish(), runs kept
+    int32_t kept;         // runs recorded before the pool ran dry
     int64_t ray;
-    int32_t chunk;        // chunk receiving runs nr.. (when nr >= kMaxRuns)
-    int32_t cur0, cur1;   // run held back for merging (cur1 > cur0 when held)
+    int32_t first;        // first pool chunk of the ray, -1 if none
+    int32_t chunk;        // last pool chunk taken
 
     __device__ __forceinline__ void begin_level(int, const Axis &, const Axis &, const Axis &) {}
-    __device__ __forceinline__ void store(const RunPool &pool, int32_t a, int32_t b) {
-        if (nr == kRunsLost) return;
-        const int j = nr % kMaxRuns;
-        if (nr < kMaxRuns) {
-            pool.slots[(int64_t)nr * pool.stride + ray] = make_int2(a, b);
-        } else {
-            if (j == 0) {
-                int32_t c = atomicAdd(pool.head, 1);
-                if (c >= pool.cap) {
-                    nr = kRunsLost;
-                    return;
-                }
-                pool.chunk_next[c] = -1;
-                if (nr == kMaxRuns) pool.ray_next[ray] = c;
-                else pool.chunk_next[chunk] = c;
-                chunk = c;
+
+    // slot k of the ray (k >= kMaxRuns: slot k % kMaxRuns of pool chunk c)
+    __device__ __forceinline__ int2 *slot(const RunPool &pool, int k, int32_t c) const {
+        return k < kMaxRuns ? pool.slots + (int64_t)k * pool.stride + ray : pool.chunks + (int64_t)c * kMaxRuns + k % kMaxRuns;
+    }
+    // records run nr; false (and the ray marked lost) if the pool is dry
+    __device__ __forceinline__ bool record(const RunPool &pool, int2 v) {
+        if (nr >= kMaxRuns && nr % kMaxRuns == 0) {
+            const int32_t c = atomicAdd(pool.head, 1);
+            if (c >= pool.cap) {
+                kept = nr;
+                nr = kRunsLost;
+                return false;
             }
-            pool.chunks[(int64_t)chunk * kMaxRuns + j] = make_int2(a, b);
+            pool.chunk_next[c] = -1;
+            if (nr == kMaxRuns) {
+                pool.ray_next[ray] = c;
+                first = c;
+            } else {
+                pool.chunk_next[chunk] = c;
+            }
+            chunk = c;
         }
+        *slot(pool, nr, chunk) = v;
         ++nr;
+        return true;
+    }
+    // lattice points of (lo, hi] up to t_max: [n0, n1), empty when n1 <= n0
+    __device__ __forceinline__ static int2 lattice_range(const Lattice &lat, float lo, float hi) {
+        return make_int2(lat.first_above(lo), lat.first_above(fminf(hi, lat.tmax)));
     }
     __device__ __forceinline__ void run(const CountCtx &x, float lo, float hi) {
-        int32_t n0 = x.lat.first_above(lo);
-        int32_t n1 = x.lat.first_above(fminf(hi, x.lat.tmax));
-        if (n1 <= n0) return;
-        n += n1 - n0;
-        if (cur1 > cur0 && cur1 == n0) {
-            cur1 = n1;
-            return;
-        }
-        if (cur1 > cur0) store(x.pool, cur0, cur1);
-        cur0 = n0;
-        cur1 = n1;
+        if (nr != kRunsLost && record(x.pool, make_int2(__float_as_int(lo), __float_as_int(hi)))) return;
+        // the pool is dry: this ray is re-walked by the fill, only its count is needed
+        const int2 q = lattice_range(x.lat, lo, hi);
+        n += max(q.y - q.x, 0);
     }
+    // Lattice ranges of the recorded runs, merged where one ends at the next's
+    // start and written back over the recorded runs (the write index never
+    // passes the read index).
     __device__ __forceinline__ void finish(const CountCtx &x) {
-        if (cur1 > cur0) store(x.pool, cur0, cur1);
-        if (nr == kRunsLost) x.pool.lost[atomicAdd(x.pool.n_lost, 1)] = (int32_t)ray;
+        const bool lost = nr == kRunsLost;
+        const int m = lost ? kept : nr;
+        int w = 0;
+        int32_t c0 = 0, c1 = 0;          // merged range held back (c1 > c0 when held)
+        int32_t rc = first, wc = first;  // pool chunks of the read and write positions
+        for (int k = 0; k < m; ++k) {
+            if (k > kMaxRuns && k % kMaxRuns == 0) rc = x.pool.chunk_next[rc];
+            const int2 raw = *slot(x.pool, k, rc);
+            const int2 q = lattice_range(x.lat, __int_as_float(raw.x), __int_as_float(raw.y));
+            if (q.y <= q.x) continue;
+            n += q.y - q.x;
+            if (c1 > c0 && c1 == q.x) {
+                c1 = q.y;
+                continue;
+            }
+            if (c1 > c0 && !lost) {
+                if (w > kMaxRuns && w % kMaxRuns == 0) wc = x.pool.chunk_next[wc];
+                *slot(x.pool, w, wc) = make_int2(c0, c1);
+                ++w;
+            }
+            c0 = q.x;
+            c1 = q.y;
+        }
+        if (c1 > c0 && !lost) {
+            if (w > kMaxRuns && w % kMaxRuns == 0) wc = x.pool.chunk_next[wc];
+            *slot(x.pool, w, wc) = make_int2(c0, c1);
+            ++w;
+        }
+        if (lost) x.pool.lost[atomicAdd(x.pool.n_lost, 1)] = (int32_t)ray;
+        else nr = w;
     }
 };
 
@@ -395,10 +437,10 @@ __device__ __forceinline__ CountVis make_count_vis(int64_t ray, const RunPool &p
     CountVis v;
     v.n = 0;
     v.nr = 0;
+    v.kept = 0;
     v.ray = ray;
+    v.first = -1;
     v.chunk = -1;
-    v.cur0 = 0;
-    v.cur1 = 0;
     pool.ray_next[ray] = -1;
     return v;
 }
@@ -725,6 +767,13 @@ constexpr int kExpandParts = 4;       // blocks sharing one chunk's windows
 constexpr int kExpandWaves = 6;
 constexpr int kGroupsPerLane = kExpandGroups / kBlock;
 constexpr int kOwnerBits = 11;        // owner entries: window number << 11 | (1 + run), run < 1024
+// The owner map is padded with one word after every kGroupsPerLane entries:
+// the max-scan has lane t read entries kGroupsPerLane*t .. +kGroupsPerLane-1,
+// which then sit at words 9t .. 9t+7; with 9 odd, the 32 lanes an LDS access
+// serves at a time meet 32 different banks (unpadded, stride 8 put four lanes
+// on every bank).
+constexpr int kOwnSlots = kExpandGroups + kExpandGroups / kGroupsPerLane;
+__device__ __forceinline__ int own_slot(int g) { return g + g / kGroupsPerLane; }
 
 struct OneLattice {       // every ray on one lattice
     static constexpr bool kMulti = false;
@@ -782,7 +831,7 @@ struct ExpandLds {
     uint32_t bn[kExpandRuns];          // n0 - start (mod 2^32): output j has lattice index bn + j
     int32_t ray[kExpandRuns];          // -1: placeholder of a lost ray
     int16_t scene[kExpandRuns];
-    uint32_t own[kExpandGroups];       // 1 + owner run of each group of the window
+    uint32_t own[kOwnSlots];           // 1 + owner run of each group of the window, at own_slot(group)
     uint32_t wmax[kBlock / 64];
     int64_t wave[kBlock / 64];
 };
@@ -804,21 +853,23 @@ __device__ __forceinline__ void expand_chunk(ExpandLds &sh, const float2 *s_lat,
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t r = r0 + threadIdx.x;
     const bool in = r < n_rays;
-    // Every global load of the staging depends on r alone, so all of them are
-    // issued here together: one memory round trip (the chunk's bounds, the
-    // ray's offsets and run count, and its first two run slots, read whether
-    // or not the ray has them; the slot arrays have a column for every ray).
+    // The chunk's bounds first (uniform loads): a part with no window of the
+    // chunk returns before it reads anything per ray.
     const int64_t base = offsets[r0];
     const int64_t bend = offsets[min(r0 + kBlock, n_rays)];
+    const int64_t lim = min(bend, capacity);
+    if (lim <= base) return;   // block-uniform: nothing to write
+    const int64_t G0 = base >> 2;   // the chunk's first group; windows count from it
+    if ((((lim - 1) >> 2) - G0) / kExpandGroups < part) return;   // block-uniform: no window of this part
+    // Every other global load of the staging depends on r alone, so all of
+    // them are issued here together: one memory round trip (the ray's offsets
+    // and run count, and its first two run slots, read whether or not the ray
+    // has them; the slot arrays have a column for every ray).
     const int64_t rc = in ? r : n_rays - 1;   // lanes past the last ray load a valid one's
     const int64_t off = offsets[rc], off_next = offsets[rc + 1];
     const int nr_rc = nruns[rc];
     const int nr_raw = in ? nr_rc : 0;
     const int2 slot0 = rd.slots[rc], slot1 = rd.slots[rd.stride + rc];
-    const int64_t lim = min(bend, capacity);
-    if (lim <= base) return;   // block-uniform: nothing to write
-    const int64_t G0 = base >> 2;   // the chunk's first group; windows count from it
-    if ((((lim - 1) >> 2) - G0) / kExpandGroups < part) return;   // block-uniform: no window of this part
     const uint32_t end_rel = (uint32_t)(bend - base);
     const uint32_t lim_rel = (uint32_t)(min(bend, capacity) - base);
     int nr = nr_raw, scene = 0;
@@ -827,7 +878,7 @@ __device__ __forceinline__ void expand_chunk(ExpandLds &sh, const float2 *s_lat,
     const uint32_t lost_len = lost ? (uint32_t)(off_next - off) : 0u;
     if (lost) nr = lost_len > 0 ? 1 : 0;
     if (in) scene = lats.scene_of(r);
-    for (int i = threadIdx.x; i < kExpandGroups; i += kBlock) s_own[i] = 0;
+    for (int i = threadIdx.x; i < kOwnSlots; i += kBlock) s_own[i] = 0;
     int64_t total;
     const int rb = (int)(block_incl_scan256((int64_t)nr, s_wave, total) - nr);
     uint32_t epoch = 0;   // window number within the block
@@ -877,7 +928,7 @@ __device__ __forceinline__ void expand_chunk(ExpandLds &sh, const float2 *s_lat,
                     // a run starting before the window marks group 0 if it is the last such run
                     // (run 0 starts at or before gw, so group 0 always holds a mark of this window)
                     if (g >= 0 || a + 1 == cn || ((base + s_start[a + 1]) >> 2) >= gw)
-                        atomicMax(&s_own[g > 0 ? g : 0], tag | (uint32_t)(a + 1));
+                        atomicMax(&s_own[own_slot(g > 0 ? (int)g : 0)], tag | (uint32_t)(a + 1));
                 }
                 __syncthreads();
                 // block-wide inclusive max-scan of s_own
@@ -885,7 +936,7 @@ __device__ __forceinline__ void expand_chunk(ExpandLds &sh, const float2 *s_lat,
                 uint32_t m = 0;
 #pragma unroll
                 for (int e = 0; e < kGroupsPerLane; ++e) {
-                    m = max(m, s_own[kGroupsPerLane * threadIdx.x + e]);
+                    m = max(m, s_own[(kGroupsPerLane + 1) * threadIdx.x + e]);
                     v[e] = m;
                 }
                 uint32_t incl = m;
@@ -901,11 +952,11 @@ __device__ __forceinline__ void expand_chunk(ExpandLds &sh, const float2 *s_lat,
                 const uint32_t below = __shfl_up(incl, 1, 64);
                 if (lane > 0) pre = max(pre, below);
 #pragma unroll
-                for (int e = 0; e < kGroupsPerLane; ++e) s_own[kGroupsPerLane * threadIdx.x + e] = max(pre, v[e]);
+                for (int e = 0; e < kGroupsPerLane; ++e) s_own[(kGroupsPerLane + 1) * threadIdx.x + e] = max(pre, v[e]);
                 __syncthreads();
                 // each lane writes groups k = tid, tid + 256, ... of the window
                 for (int k = threadIdx.x; k < nwin; k += kBlock) {
-                    const int a = (int)(s_own[k] & ((1u << kOwnerBits) - 1)) - 1;   // owns the group's last output
+                    const int a = (int)(s_own[own_slot(k)] & ((1u << kOwnerBits) - 1)) - 1;   // owns the group's last output
                     const int64_t j4 = 4 * (gw + k) - base;       // block-relative, may lie below lo
                     // runs a-1, a-2, a-3 may own the group's earlier outputs
                     const uint32_t sa = s_start[a];
