@@ -152,8 +152,10 @@ def cascades_side(api, torch, scenes, steps, warmup):
     o = torch.from_numpy(w.origins).cuda()
     d = torch.from_numpy(w.dirs).cuda()
     out = {"rays": w.n_rays, "levels": int(w.occ.shape[0])}
-    for name, grid in (("vdb", api.build_vdb(occ, w.boxes, w.ilog2)), ("dense", api.build_dense(occ, w.boxes))):
-        t = Timed(api, torch, grid, w, o, d, "branch", w.image[0])
+    vdb = api.build_vdb(occ, w.boxes, w.ilog2)
+    for name, grid, variant in (("vdb", vdb, "branch"), ("vdb_subleaf", vdb, "subleaf_branch"),
+                                ("dense", api.build_dense(occ, w.boxes), "branch")):
+        t = Timed(api, torch, grid, w, o, d, variant, w.image[0])
         ms, walk, scan, fill = t.run(steps, warmup)
         N, S, G = w.n_rays, t.S, grid.info()["bytes"]
         step_bytes = 24 * N + 8 * (N + 1) + 12 * S + G   # the call's inputs and outputs, as for the headline
@@ -162,6 +164,7 @@ def cascades_side(api, torch, scenes, steps, warmup):
                      "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del t
     out["speedup_vs_dense"] = out["dense"]["ms_per_step"] / out["vdb"]["ms_per_step"]
+    out["subleaf_speedup_vs_dense"] = out["dense"]["ms_per_step"] / out["vdb_subleaf"]["ms_per_step"]
     return out
 
 
@@ -353,7 +356,9 @@ def main():
         # the same tree walked one voxel per step ("VDB + DDA", Tab. 1-2)
         vox = Timed(api, torch, vdb, w, o, d, "voxel_" + args.variant, W)
         vox_other = Timed(api, torch, vdb, w, o, d, "voxel_" + other, W)
-        assert hdda.S == plain.S == hdda_other.S == plain_skip.S == chess.S == vox.S == vox_other.S, \
+        # hierarchical steps that also pass uniform sub-blocks inside leaves
+        sub = Timed(api, torch, vdb, w, o, d, "subleaf_" + args.variant, W)
+        assert hdda.S == plain.S == hdda_other.S == plain_skip.S == chess.S == vox.S == vox_other.S == sub.S, \
             "samplers disagree on the sample count"
         N_ = w.n_rays
 
@@ -372,6 +377,7 @@ def main():
         compare["chessboard"] = dict(rec(chess), bytes=distg.info()["bytes"])
         compare["vdb_voxel_steps"] = rec(vox)
         compare["vdb_voxel_steps_" + other] = rec(vox_other)
+        compare["vdb_subleaf"] = rec(sub)
         compare["speedup_vs_dense"] = compare["dense"]["ms_per_step"] / ms
     count_ms = walk_ms + scan_ms
     N, S = w.n_rays, hdda.S

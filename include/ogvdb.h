@@ -65,19 +65,24 @@ typedef int32_t ogv_status;
  * OGV_VOXEL may be or-ed into either, for VDB grids only: the tree is then
  * walked one voxel per step, each voxel's occupancy looked up in the tree and
  * no tile skipped in one step (the "VDB + DDA" rows of Tab. 1-2, against the
- * default hierarchical steps of "VDB + HDDA").  A sampling call rejects it on
- * any other grid with OGV_ERR_INVALID; batches take OGV_BRANCH or OGV_SKIP
- * only.  Every variant gives identical samples. */
+ * default hierarchical steps of "VDB + HDDA").  OGV_SUBLEAF (VDB grids only,
+ * not with OGV_VOXEL) makes the hierarchical steps go on below the leaf
+ * level: a uniform 4^3 or 2^3 sub-block of a leaf (all empty or all
+ * occupied) is passed in one step, so empty space is skipped by powers of two
+ * down to single voxels (Fig. 1).  A sampling call rejects either on any
+ * other grid with OGV_ERR_INVALID; batches take OGV_BRANCH or OGV_SKIP only.
+ * Every variant gives identical samples. */
 #define OGV_BRANCH 0
 #define OGV_SKIP 1
 #define OGV_VOXEL 2
+#define OGV_SUBLEAF 4
 
 /* Options of a sampling call (NULL means {OGV_BRANCH, 0}).  image_width > 0
  * says the rays are the row-major pixels of an image that wide; lanes then
  * take 8x8 pixel tiles so neighbouring rays walk together.  It changes only
  * speed, never the samples or their order. */
 typedef struct {
-    int32_t variant;      /* OGV_BRANCH or OGV_SKIP, optionally | OGV_VOXEL */
+    int32_t variant;      /* OGV_BRANCH or OGV_SKIP, optionally | OGV_VOXEL or | OGV_SUBLEAF */
     int32_t image_width;  /* >= 0 */
 } ogv_sample_opts;
 

@@ -13,7 +13,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libogvdb.so")
 
-BRANCH, SKIP, VOXEL = 0, 1, 2
+BRANCH, SKIP, VOXEL, SUBLEAF = 0, 1, 2, 4
 STEP_CONST, STEP_CONE = 0, 1
 
 
@@ -138,8 +138,11 @@ def make_step(kind="const", dt=0.0, cone=0.0, dt_min=0.0):
 
 def _variant(v):
     """Loop variant: "branch", "skip", "voxel_branch", "voxel_skip" (VDB grids
-    walked one voxel per step) or the ogvdb.h value."""
-    names = {"branch": BRANCH, "skip": SKIP, "voxel_branch": BRANCH | VOXEL, "voxel_skip": SKIP | VOXEL}
+    walked one voxel per step), "subleaf_branch", "subleaf_skip" (VDB grids
+    walked with steps over uniform sub-blocks of leaves too) or the ogvdb.h
+    value."""
+    names = {"branch": BRANCH, "skip": SKIP, "voxel_branch": BRANCH | VOXEL, "voxel_skip": SKIP | VOXEL,
+             "subleaf_branch": BRANCH | SUBLEAF, "subleaf_skip": SKIP | SUBLEAF}
     if isinstance(v, str):
         return names[v]
     if v not in names.values():

@@ -256,9 +256,38 @@ __global__ void __launch_bounds__(256) node_write_kernel(BuildDims b, const int3
     }
 }
 
+// Uniform sub-blocks of a leaf given its eight words (word x, bit y*8 + z):
+// u2 bit ((x>>1)*4 + (y>>1))*4 + (z>>1) is set when the eight voxels of that
+// 2^3 sub-block are all occupied or all empty, u4 bit ((x>>2)*2 + (y>>2))*2 +
+// (z>>2) likewise for the 64 voxels of a 4^3 sub-block.
+__device__ void leaf_uniform_subblocks(const uint64_t *w, uint64_t &u2, uint64_t &u4) {
+    u2 = 0;
+    u4 = 0;
+    for (int xp = 0; xp < 4; ++xp) {
+        const uint64_t a = w[2 * xp] & w[2 * xp + 1], o = w[2 * xp] | w[2 * xp + 1];
+        for (int yp = 0; yp < 4; ++yp)
+            for (int zp = 0; zp < 4; ++zp) {
+                const uint64_t m = 0x303ull << (16 * yp + 2 * zp);   // y in {2yp, 2yp+1}, z in {2zp, 2zp+1}
+                if ((a & m) == m || (o & m) == 0) u2 |= 1ull << ((xp * 4 + yp) * 4 + zp);
+            }
+    }
+    for (int xq = 0; xq < 2; ++xq) {
+        uint64_t a = ~0ull, o = 0;
+        for (int x = 4 * xq; x < 4 * xq + 4; ++x) {
+            a &= w[x];
+            o |= w[x];
+        }
+        for (int yq = 0; yq < 2; ++yq)
+            for (int zq = 0; zq < 2; ++zq) {
+                const uint64_t m = 0x0F0F0F0Full << (32 * yq + 4 * zq);   // y in 4yq..4yq+3, z in 4zq..4zq+3
+                if ((a & m) == m || (o & m) == 0) u4 |= 1ull << ((xq * 2 + yq) * 2 + zq);
+            }
+    }
+}
+
 __global__ void leaf_write_kernel(BuildDims b, const int32_t *__restrict__ mixed, const int64_t *__restrict__ leaf_idx,
                                   const uint64_t *__restrict__ masks, uint64_t *__restrict__ leaves,
-                                  VdbCounts *counts) {
+                                  uint64_t *__restrict__ sub, VdbCounts *counts) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t e = t >> 3;
     int j = (int)(t & 7);
@@ -266,6 +295,12 @@ __global__ void leaf_write_kernel(BuildDims b, const int32_t *__restrict__ mixed
     if (e == 0 && j == 0) counts->n_leaves = leaf_idx[b.n_block];
     if (!mixed[e]) return;
     leaves[leaf_idx[e] * 8 + j] = masks[e * 8 + j];
+    if (j == 0) {
+        uint64_t u2, u4;
+        leaf_uniform_subblocks(masks + e * 8, u2, u4);
+        sub[leaf_idx[e] * 2] = u2;
+        sub[leaf_idx[e] * 2 + 1] = u4;
+    }
 }
 
 // decode a VDB tree into dense bytes, one thread per voxel
@@ -356,8 +391,8 @@ hipError_t enqueue_vdb(ogv_grid *g, const VdbBuildState &st, const uint8_t *occ,
         node_write_kernel<<<(unsigned)((b.n_root * b.W + 3) / 4), 256, 0, s>>>(
             b, st.root_kind, st.node_idx, st.kind, st.leaf_idx, (uint64_t *)v.child, (uint64_t *)v.value,
             (uint32_t *)v.rank, (int32_t *)v.slot, g->counts_dev);
-        leaf_write_kernel<<<(unsigned)((b.n_block * 8 + 255) / 256), 256, 0, s>>>(b, st.mixed, st.leaf_idx, st.masks,
-                                                                                 (uint64_t *)v.leaves, g->counts_dev);
+        leaf_write_kernel<<<(unsigned)((b.n_block * 8 + 255) / 256), 256, 0, s>>>(
+            b, st.mixed, st.leaf_idx, st.masks, (uint64_t *)v.leaves, (uint64_t *)v.sub, g->counts_dev);
         e = hipGetLastError();
     }
     return e;
@@ -517,6 +552,7 @@ extern "C" ogv_status ogv_vdb_build(int32_t L, int32_t R, const float *boxes, co
     size_t o_rank = take(sizeof(uint32_t) * b.n_root * b.W);
     size_t o_slot = take(sizeof(int32_t) * b.n_root * b.n_slot);
     size_t o_leaves = take(sizeof(uint64_t) * 8 * b.n_block);
+    size_t o_sub = take(sizeof(uint64_t) * 2 * b.n_block);
     size_t total = off;
     // build scratch
     off = 0;
@@ -566,6 +602,7 @@ extern "C" ogv_status ogv_vdb_build(int32_t L, int32_t R, const float *boxes, co
     v.rank = (const uint32_t *)(m + o_rank);
     v.slot = (const int32_t *)(m + o_slot);
     v.leaves = (const uint64_t *)(m + o_leaves);
+    v.sub = (const uint64_t *)(m + o_sub);
     g->counts_dev = (VdbCounts *)(m + o_counts);
 
     bs->kind = (int32_t *)(t + t_kind);
@@ -615,7 +652,7 @@ extern "C" ogv_status ogv_grid_info_get(const ogv_grid *grid, ogv_grid_info *inf
         g->counts_ready = true;
         const int64_t n_root = (int64_t)v.L * v.NR * v.NR * v.NR;
         g->used_bytes = (size_t)(n_root * 4 + g->counts_host.n_nodes * (int64_t)v.W * (8 + 8 + 4) +
-                                 g->counts_host.n_nodes * (int64_t)v.S * v.S * v.S * 4 + g->counts_host.n_leaves * 64);
+                                 g->counts_host.n_nodes * (int64_t)v.S * v.S * v.S * 4 + g->counts_host.n_leaves * (64 + 16));
     }
     const VdbCounts &c = g->counts_host;
     info->bytes = (int64_t)g->used_bytes;

@@ -269,9 +269,12 @@ ogv_status validate_sampling(const ogv_grid *grid, int32_t variant, const float 
                     float near_t, float far_t, const ogv_step *step, const char *fn) {
     std::string f(fn);
     if (!grid) OGV_FAIL(OGV_ERR_INVALID, f + ": grid is null");
-    if (variant < 0 || variant > (OGV_SKIP | OGV_VOXEL)) OGV_FAIL(OGV_ERR_INVALID, f + ": variant must be 0..3");
-    if ((variant & OGV_VOXEL) && grid->view.kind != 1)
-        OGV_FAIL(OGV_ERR_INVALID, f + ": OGV_VOXEL walks a VDB grid; this grid is not one");
+    if (variant < 0 || variant > (OGV_SKIP | OGV_VOXEL | OGV_SUBLEAF))
+        OGV_FAIL(OGV_ERR_INVALID, f + ": variant must be 0..7");
+    if ((variant & OGV_VOXEL) && (variant & OGV_SUBLEAF))
+        OGV_FAIL(OGV_ERR_INVALID, f + ": OGV_VOXEL and OGV_SUBLEAF exclude each other");
+    if ((variant & (OGV_VOXEL | OGV_SUBLEAF)) && grid->view.kind != 1)
+        OGV_FAIL(OGV_ERR_INVALID, f + ": OGV_VOXEL and OGV_SUBLEAF walk a VDB grid; this grid is not one");
     if (n_rays < 0 || n_rays > (int64_t)INT32_MAX) OGV_FAIL(OGV_ERR_INVALID, f + ": n_rays out of range");
     if (n_rays > 0 && (!o || !d)) OGV_FAIL(OGV_ERR_INVALID, f + ": null ray pointer");
     if (!step) OGV_FAIL(OGV_ERR_INVALID, f + ": step is null");
@@ -413,7 +416,9 @@ void launch_fill(const GridView &g, const float *o, const float *d, int64_t n, c
 
 // Traversal of a call (the CursorOf index): the grid's kind, or 3 for a VDB
 // grid walked one voxel per step.
-int traversal_of(const GridView &g, int variant) { return (variant & OGV_VOXEL) ? 3 : g.kind; }
+int traversal_of(const GridView &g, int variant) {
+    return (variant & OGV_VOXEL) ? 3 : (variant & OGV_SUBLEAF) ? 4 : g.kind;
+}
 
 // Calls OGV_LAUNCH(traversal, skip, tree in LDS) with the instantiation that
 // serves (g, variant).
@@ -436,6 +441,12 @@ int traversal_of(const GridView &g, int variant) { return (variant & OGV_VOXEL) 
             else if (lds_) OGV_LAUNCH(3, false, true);                   \
             else OGV_LAUNCH(3, false, false);                            \
             break;                                                       \
+        case 4:                                                          \
+            if (sk_ && lds_) OGV_LAUNCH(4, true, true);                  \
+            else if (sk_) OGV_LAUNCH(4, true, false);                    \
+            else if (lds_) OGV_LAUNCH(4, false, true);                   \
+            else OGV_LAUNCH(4, false, false);                            \
+            break;                                                       \
         default:                                                         \
             if (sk_ && lds_) OGV_LAUNCH(1, true, true);                  \
             else if (sk_) OGV_LAUNCH(1, true, false);                    \
@@ -446,7 +457,7 @@ int traversal_of(const GridView &g, int variant) { return (variant & OGV_VOXEL) 
 
 void dispatch_count(const GridView &g, int variant, const float *o, const float *d, int64_t n, const Lattice &lat,
                     const Bufs &b, int width, hipStream_t s) {
-#define OGV_LAUNCH(V, K, L) launch_count<V, K, (V == 1 || V == 3) && L>(g, o, d, n, lat, b, width, s)
+#define OGV_LAUNCH(V, K, L) launch_count<V, K, reads_tree(V) && L>(g, o, d, n, lat, b, width, s)
     OGV_DISPATCH(g, variant);
 #undef OGV_LAUNCH
 }
@@ -454,7 +465,7 @@ void dispatch_count(const GridView &g, int variant, const float *o, const float 
 void dispatch_fill(const GridView &g, int variant, const float *o, const float *d, int64_t n, const Lattice &lat,
                    const int64_t *offsets, int64_t cap, int32_t *ids, float *t0, float *t1, int32_t *vox,
                    hipStream_t s) {
-#define OGV_LAUNCH(V, K, L) launch_fill<V, K, (V == 1 || V == 3) && L>(g, o, d, n, lat, offsets, cap, ids, t0, t1, vox, s)
+#define OGV_LAUNCH(V, K, L) launch_fill<V, K, reads_tree(V) && L>(g, o, d, n, lat, offsets, cap, ids, t0, t1, vox, s)
     OGV_DISPATCH(g, variant);
 #undef OGV_LAUNCH
 }

@@ -71,6 +71,7 @@ struct Tree {
     const int32_t *root;
     const int32_t *slot;
     const uint64_t *leaves;
+    const uint64_t *sub;   // [leaves][2]: uniform 2^3 and 4^3 sub-blocks
     int ilog2, S, NR;
 };
 
@@ -106,6 +107,7 @@ __device__ __forceinline__ Tree load_tree(const GridView &g, uint32_t *smem) {
     t.S = g.S;
     t.NR = g.NR;
     t.leaves = g.leaves;
+    t.sub = g.sub;
     if (!kLds) {
         t.root = g.root;
         t.slot = g.slot;
@@ -126,8 +128,12 @@ __device__ __forceinline__ Tree load_tree(const GridView &g, uint32_t *smem) {
 
 // VDB tree: the current cell is the largest uniform cell holding the current
 // voxel -- a root tile (D = 8*S voxels per axis), an internal-node tile
-// (D = 8) or a leaf voxel (D = 1).  Its exit is the first crossing of its far
-// planes (for D = 1 the ordinary voxel step).
+// (D = 8) or a leaf voxel (D = 1); with kSub, inside a leaf also a uniform
+// 4^3 or 2^3 sub-block (D = 4, 2: all its voxels empty, or all occupied), so
+// that the cells nest as aligned cubes whose side halves level by level and a
+// step passes empty space by powers of two down to single voxels (Fig. 1).
+// The cell's exit is the first crossing of its far planes (for D = 1 the
+// ordinary voxel step).
 //
 // The walk is incremental, as in a plain DDA: a step moves the stepping axis
 // into the next cell and looks that cell up; when it has the same size as the
@@ -142,7 +148,13 @@ __device__ __forceinline__ Tree load_tree(const GridView &g, uint32_t *smem) {
 // "VDB + DDA" rows, Tab. 1-2): a voxel inside a tile takes the tile's value
 // and the walk moves on to the next voxel, so the tree only changes how
 // occupancy is looked up, not which cells are visited.
-template <bool kTiles>
+//
+// kSub trades steps for dearer ones: on the object-scene workload it takes
+// about 30% fewer steps, but the cell size changes about four times as often
+// inside leaves, and each change recomputes all exits (and, going down,
+// re-locates the other axes and looks the cell up again), in some lane of
+// nearly every step of a wave.
+template <bool kTiles, bool kSub = false>
 struct VdbWalk {
     Tree t;
     int lev, R, sh;
@@ -156,6 +168,8 @@ struct VdbWalk {
     bool occ;              // current cell occupied
     int lblk;              // cached leaf block (packed block coordinates), -1 if none
     int lbase;             // its first word in the leaf array
+    uint64_t lu2;          // its uniform 2^3 sub-blocks (Tree::sub word 0)
+    uint32_t lu4;          // its uniform 4^3 sub-blocks (Tree::sub word 1)
 
     // Size of the largest uniform cell holding voxel (v0, v1, v2) and its
     // occupancy.  A voxel in the cached leaf block (most voxel steps) needs
@@ -178,6 +192,11 @@ struct VdbWalk {
             if (!root_tile && !slot_tile) {
                 lblk = blk;
                 lbase = c * 8;
+                if (kSub) {
+                    const uint4 u = *reinterpret_cast<const uint4 *>(t.sub + 2 * c);
+                    lu2 = (uint64_t)u.y << 32 | u.x;
+                    lu4 = u.z;
+                }
             } else {
                 o = root_tile ? node == -2 : c == -2;
                 return kTiles ? (root_tile ? (8 << t.ilog2) : 8) : 1;
@@ -187,6 +206,15 @@ struct VdbWalk {
         const int bit = ((v1 & 7) << 3) | (v2 & 7);
         const uint32_t half = bit < 32 ? (uint32_t)word : (uint32_t)(word >> 32);
         o = ((half >> (bit & 31)) & 1u) != 0;
+        if (kSub) {
+            // a uniform sub-block takes the voxel's value: the largest one holding it is the cell
+            const int s2 = (((v0 >> 1) & 3) << 4) | (((v1 >> 1) & 3) << 2) | ((v2 >> 1) & 3);
+            const int s4 = (((v0 >> 2) & 1) << 2) | (((v1 >> 2) & 1) << 1) | ((v2 >> 2) & 1);
+            const uint32_t h2 = s2 < 32 ? (uint32_t)lu2 : (uint32_t)(lu2 >> 32);
+            const bool u2 = ((h2 >> (s2 & 31)) & 1u) != 0;
+            const bool u4 = ((lu4 >> s4) & 1u) != 0;
+            D = u4 ? 4 : (u2 ? 2 : 1);
+        }
         return D;
     }
 
@@ -582,8 +610,9 @@ struct Ray {
 };
 
 // Traversals: 0 dense bitfield, 1 VDB tree with hierarchical steps, 2 dense
-// bitfield with chessboard distances (GridView::kind 0, 1, 2), and 3 the VDB
-// tree walked one voxel per step (a kind-1 grid).
+// bitfield with chessboard distances (GridView::kind 0, 1, 2), 3 the VDB
+// tree walked one voxel per step and 4 the VDB tree with hierarchical steps
+// that also pass uniform sub-blocks inside leaves (both on kind-1 grids).
 template <int kGrid>
 struct CursorOf {
     using type = DenseCursor;
@@ -600,9 +629,13 @@ template <>
 struct CursorOf<3> {
     using type = VdbWalk<false>;
 };
+template <>
+struct CursorOf<4> {
+    using type = VdbWalk<true, true>;
+};
 
 // Traversals that read the VDB tree.
-constexpr bool reads_tree(int kGrid) { return kGrid == 1 || kGrid == 3; }
+constexpr bool reads_tree(int kGrid) { return kGrid == 1 || kGrid == 3 || kGrid == 4; }
 
 // Puts the cursor of level `lev` on the voxel owning t_min when t_min lies
 // after the segment start a, else on the voxel owning the parameters just
@@ -648,6 +681,8 @@ __device__ __forceinline__ bool cursor_begin(typename CursorOf<kGrid>::type &c, 
         c.k0 = c.k1 = c.k2 = 0;
         c.lblk = -1;
         c.lbase = 0;
+        c.lu2 = 0;
+        c.lu4 = 0;
         c.enter();
     }
     return true;

@@ -74,7 +74,7 @@ def test_batch_matches_oracle_reduced(kind):
 def test_batch_rejects_voxel_steps():
     # a batch walks each VDB hierarchically; OGV_VOXEL is a single-scene option
     ws = scenes.batched(n_scenes=2, ray_sides=[64, 64])
-    for v in ("voxel_branch", "voxel_skip"):
+    for v in ("voxel_branch", "voxel_skip", "subleaf_branch", "subleaf_skip"):
         with pytest.raises(api.OgvError):
             api.Batch(_gpu_scenes(ws), v, tune=(256, 2))
 

@@ -17,7 +17,8 @@ from tests import handmade
 pytestmark = pytest.mark.gpu
 
 VARIANTS = [("dense", "branch"), ("dense", "skip"), ("vdb", "branch"), ("vdb", "skip"), ("vdb", "voxel_branch"),
-            ("vdb", "voxel_skip"), ("dist", "branch"), ("dist", "skip")]
+            ("vdb", "voxel_skip"), ("vdb", "subleaf_branch"), ("vdb", "subleaf_skip"), ("dist", "branch"),
+            ("dist", "skip")]
 _VID = lambda v: f"{v[0]}-{v[1]}"
 
 
@@ -302,21 +303,23 @@ def test_invalid_arguments_raise(small):
 
 
 def test_voxel_steps_only_on_vdb_grids(small):
-    """OGV_VOXEL names a way to walk a VDB tree: a dense or distance grid
-    rejects it, and an undefined variant bit is rejected on every grid."""
+    """OGV_VOXEL and OGV_SUBLEAF name ways to walk a VDB tree: a dense or
+    distance grid rejects them, the two together are rejected, and an
+    undefined variant bit is rejected on every grid."""
     o = torch.from_numpy(small.origins[:64]).cuda()
     d = torch.from_numpy(small.dirs[:64]).cuda()
     step = api.make_step(small.step)
     for kind in ("dense", "dist"):
         g = gpu_grid(kind, small.occ, small.boxes, small.ilog2)
-        for v in ("voxel_branch", "voxel_skip"):
+        for v in ("voxel_branch", "voxel_skip", "subleaf_branch", "subleaf_skip"):
             with pytest.raises(api.OgvError):
                 api.sample_rays(g, o, d, small.near, small.far, step, v)
     g = gpu_grid("vdb", small.occ, small.boxes, small.ilog2)
     sp = api.Sampler(g, 64, small.near, small.far, step)
-    sp.opts.variant = 4
-    with pytest.raises(api.OgvError):
-        sp.count(o, d)
+    for bad in (api.VOXEL | api.SUBLEAF, 8):
+        sp.opts.variant = bad
+        with pytest.raises(api.OgvError):
+            sp.count(o, d)
 
 
 def test_determinism(obj):

@@ -95,12 +95,15 @@ def test_variant_names_map_to_header_values():
     # the binding's loop-variant names follow ogvdb.h's OGV_BRANCH, OGV_SKIP, OGV_VOXEL
     from paper_2404_10272_amd import api
     text = open(HEADER).read()
-    vals = {k: int(v) for k, v in re.findall(r"#define (OGV_BRANCH|OGV_SKIP|OGV_VOXEL) (\d+)", text)}
-    assert (api.BRANCH, api.SKIP, api.VOXEL) == (vals["OGV_BRANCH"], vals["OGV_SKIP"], vals["OGV_VOXEL"])
+    vals = {k: int(v) for k, v in re.findall(r"#define (OGV_BRANCH|OGV_SKIP|OGV_VOXEL|OGV_SUBLEAF) (\d+)", text)}
+    assert (api.BRANCH, api.SKIP, api.VOXEL, api.SUBLEAF) == (vals["OGV_BRANCH"], vals["OGV_SKIP"], vals["OGV_VOXEL"],
+                                                              vals["OGV_SUBLEAF"])
     assert api._variant("voxel_branch") == api.BRANCH | api.VOXEL
     assert api._variant("voxel_skip") == api.SKIP | api.VOXEL
+    assert api._variant("subleaf_skip") == api.SKIP | api.SUBLEAF
     assert api._variant(3) == 3
-    with pytest.raises(ValueError):
-        api._variant(4)
+    for bad in (6, 8):
+        with pytest.raises(ValueError):
+            api._variant(bad)
     with pytest.raises(KeyError):
         api._variant("voxel")
