@@ -252,6 +252,60 @@ def _median3(fn):
     return sorted(ts)[1], out
 
 
+def refresh_side(api, torch, scenes, steps):
+    """In-place VDB refresh at 128^3 (the object grid) and 256^3 (the same
+    grid upsampled twofold): the full re-classify from a uint8 occupancy, and
+    the density-cache refresh (threshold fused into the classification) on
+    its two paths -- bits changed only inside leaves (the tree keeps its
+    numbering; the changed leaves are rewritten) and block kinds changed (the
+    tree is renumbered).  Each call alternates between two densities that
+    differ in that way, with decay 0, so every call changes the grid."""
+    import numpy as np
+    w = scenes.workload("object")
+    rng = np.random.default_rng(9100)
+    out = {}
+    for R in (128, 256):
+        occ = w.occ if R == 128 else np.repeat(np.repeat(np.repeat(w.occ, 2, 1), 2, 2), 2, 3)
+        occ = np.ascontiguousarray(occ)
+        dens = np.where(occ > 0, rng.uniform(2.0, 20.0, occ.shape), rng.uniform(0.0, 0.9, occ.shape))
+        a = dens.astype(np.float32)
+        # b: one occupied voxel cleared in 200 mixed blocks holding at least two (kinds unchanged)
+        L = occ.shape[0]
+        cnt = occ.reshape(L, R // 8, 8, R // 8, 8, R // 8, 8).sum(axis=(2, 4, 6))
+        cand = np.argwhere((cnt >= 2) & (cnt < 512))
+        b = a.copy()
+        for l, bx, by, bz in cand[rng.choice(len(cand), 200, replace=False)]:
+            i, j, k = np.argwhere(occ[l, 8 * bx:8 * bx + 8, 8 * by:8 * by + 8, 8 * bz:8 * bz + 8])[0]
+            b[l, 8 * bx + i, 8 * by + j, 8 * bz + k] = 0.0
+        c = a.copy()
+        c[:, : R // 4] = 0.0                      # a quarter of the grid emptied: leaves and tiles change
+        occ_d = torch.from_numpy(occ).cuda()
+        g = api.build_vdb(occ_d, w.boxes, w.ilog2)
+        cache = torch.from_numpy(a).cuda()
+        A, B, C = (torch.from_numpy(x).cuda() for x in (a, b, c))
+        changed = torch.zeros(2, dtype=torch.int32, device="cuda")
+        state = {"i": 0}
+
+        def alternate(x, y):
+            def f():
+                state["i"] += 1
+                g.refresh_density(cache, x if state["i"] % 2 else y, 0.0, 1.0, changed)
+            return f
+
+        rec = {"voxels": int(occ.size), "full_reclassify_uint8_ms": time_events(torch, lambda: g.refresh(occ_d), steps, 2)}
+        rec["density_leaves_only_ms"] = time_events(torch, alternate(A, B), steps, 2)
+        torch.cuda.synchronize()
+        rec["leaves_only_changed"] = changed.cpu().tolist()
+        rec["density_structure_ms"] = time_events(torch, alternate(A, C), steps, 2)
+        torch.cuda.synchronize()
+        rec["structure_changed"] = changed.cpu().tolist()
+        rec["density_threshold_only_ms"] = time_events(
+            torch, lambda: g.refresh_density(cache, None, 0.0, 1.0, changed), steps, 2)
+        out[f"{R}^3"] = rec
+        del g, cache, A, B, C, occ_d
+    return out
+
+
 def cpu_baseline(obj_stride=1, unb_stride=2):
     """The oracle as it stands (count + fill of every ray, OpenMP over rays),
     timed on the host cores: the plain dense DDA (O2) and the VDB +
@@ -464,6 +518,7 @@ def main():
         line["batched"] = batched_side(api, torch, scenes, min(args.steps, 10))
         line["cascades"] = cascades_side(api, torch, scenes, min(args.steps, 10), 2)
         line["render"] = render_side(api, torch, scenes, hdda, w, min(args.steps, 20))
+        line["refresh"] = refresh_side(api, torch, scenes, min(args.steps, 20))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.cpu_stride)
     print(json.dumps(line), flush=True)

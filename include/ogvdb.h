@@ -171,6 +171,34 @@ void ogv_grid_destroy(ogv_grid *grid);
  * arguments. */
 ogv_status ogv_grid_refresh(ogv_grid *grid, const uint8_t *occ_dev, void *stream);
 
+/* Refreshes a grid from a density cache (Sec. 2.1: the occupancy grid
+ * caches the densities the field predicts during training, and samples come
+ * from the voxels whose cached density exceeds a threshold; the paper's
+ * training refreshes it every 16 iterations, Sec. 4.1, and names low-cost
+ * pruning on the GPU as future work, Sec. 5).  In place and asynchronous on
+ * the stream, no allocation and no host synchronization.
+ *   cache_dev    float32 [n_levels][res][res][res] (the grid's layout),
+ *                caller-owned.  With density_dev non-null every entry is
+ *                first updated in place to max(decay*cache, density): one
+ *                binary32 product, then density when it is larger, else the
+ *                product.  Entries must not be NaN.
+ *   density_dev  nullable float32, same layout: the field's new densities.
+ *   decay        in [0, 1] (checked only when density_dev is given).
+ *   threshold    a voxel is occupied when its (updated) cache value is
+ *                greater than this.
+ *   changed_dev  nullable int32 [2], written on the stream: [0] the number
+ *                of voxels whose occupancy changed, [1] 1 if the VDB tree's
+ *                structure changed (some 8^3 block became empty, full or
+ *                mixed), else 0 (always 0 for other grids).
+ * The threshold is fused into the pass that classifies the 8^3 blocks, which
+ * also compares each block's bits with the previous ones.  A VDB tree is
+ * renumbered and rewritten only when some block changed kind; otherwise
+ * just the leaves whose bits changed are rewritten.  Ordering and the use of
+ * ogv_grid_info_get afterwards as for ogv_grid_refresh.  OGV_ERR_INVALID on
+ * null grid or cache, a decay outside [0, 1] or a NaN threshold. */
+ogv_status ogv_grid_refresh_density(ogv_grid *grid, float *cache_dev, const float *density_dev, float decay,
+                                    float threshold, int32_t *changed_dev, void *stream);
+
 /* Workspace bytes a sample call needs for n_rays rays and this lattice.
  * With a growing step (OGV_STEP_CONE) the workspace also keeps the lattice's
  * point table between calls, beside a header with near, far, cone, dt_min,

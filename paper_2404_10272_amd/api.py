@@ -74,6 +74,7 @@ SIGNATURES = {
     "ogv_grid_to_dense": (I32, [VP, VP, VP]),
     "ogv_grid_destroy": (None, [VP]),
     "ogv_grid_refresh": (I32, [VP, VP, VP]),
+    "ogv_grid_refresh_density": (I32, [VP, VP, VP, F32, F32, VP, VP]),
     "ogv_sample_workspace_size": (I32, [I64, F32, F32, ctypes.POINTER(_Step), ctypes.POINTER(SZ)]),
     "ogv_sample_count": (I32, [VP, ctypes.POINTER(_Opts), VP, VP, I64, F32, F32, ctypes.POINTER(_Step), VP, VP, SZ,
                                VP]),
@@ -187,6 +188,26 @@ class Grid:
             raise OgvError(f"occupancy shape {tuple(occ.shape)} differs from the grid's {tuple(self.shape)}")
         _check(lib().ogv_grid_refresh(self._h, _ptr(occ), _stream(stream)))
         self._occ_in_use = occ
+
+    def refresh_density(self, cache, density=None, decay=0.95, threshold=0.01, changed=None, stream=None):
+        """Re-derives this grid from a float32 density cache of its shape, in
+        place and asynchronously: with `density`, the cache is first updated
+        to max(decay*cache, density); a voxel is occupied when its cache
+        value exceeds `threshold`.  `changed` (int32 [2], optional) receives
+        the number of voxels that changed and whether the tree's structure
+        did."""
+        for t in (cache, density):
+            if t is None:
+                continue
+            if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+                raise OgvError("density tensors must be contiguous float32 device tensors")
+            if self.shape is not None and tuple(t.shape) != tuple(self.shape):
+                raise OgvError(f"density shape {tuple(t.shape)} differs from the grid's {tuple(self.shape)}")
+        if changed is not None and (changed.dtype != torch.int32 or changed.numel() < 2 or not changed.is_cuda):
+            raise OgvError("changed must be an int32 device tensor of 2 entries")
+        _check(lib().ogv_grid_refresh_density(self._h, _ptr(cache), _ptr(density), float(decay), float(threshold),
+                                              _ptr(changed), _stream(stream)))
+        self._occ_in_use = (cache, density)
 
     def distances(self):
         """A distance grid's capped chessboard distances, uint8 [L][R][R][R]."""

@@ -68,23 +68,93 @@ namespace {
 
 // ------------------------------------------------------------------ dense
 
-__global__ void dense_pack_kernel(const uint8_t *__restrict__ occ, uint64_t n_vox, uint32_t *__restrict__ bits,
-                                  uint64_t n_words) {
-    uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= n_words) return;
-    uint32_t word = 0;
-    uint64_t base = w * 32;
-    for (int j = 0; j < 32; ++j) {
-        uint64_t i = base + j;
-        if (i < n_vox && occ[i] != 0) word |= 1u << j;
-    }
-    bits[w] = word;
+// one voxel per lane: a wave's 64 consecutive voxels form two words
+__global__ void __launch_bounds__(256) dense_pack_kernel(const uint8_t *__restrict__ occ, uint64_t n_vox,
+                                                        uint32_t *__restrict__ bits) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t m = __ballot(i < n_vox && occ[i] != 0);
+    const int lane = threadIdx.x & 63;
+    if ((lane == 0 || lane == 32) && i < n_vox) bits[i >> 5] = lane == 0 ? (uint32_t)m : (uint32_t)(m >> 32);
 }
 
 __global__ void dense_unpack_kernel(const uint32_t *__restrict__ bits, uint64_t n_vox, uint8_t *__restrict__ out) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_vox) return;
     out[i] = (bits[i >> 5] >> (i & 31)) & 1u;
+}
+
+// A dense or distance grid's allocation: boxes at 0 (<= 192 bytes), plane
+// geometry at 512 (<= 384 bytes), a density refresh's two change counters at
+// kDenseChanged, the bitfield from 1024.
+constexpr size_t kDenseChanged = 960;
+
+// ------------------------------------------------------------------ density cache
+
+// One refresh from a density cache (Sec. 2.1: the grid caches the field's
+// predicted densities, and samples are taken in the voxels whose cached
+// density exceeds a threshold).  With a new density d the cached value c
+// becomes max(decay*c, d) -- one binary32 product, then the larger value
+// (taken as d when d > decay*c, else decay*c) -- and is written back; the
+// voxel is occupied when the (updated) cached value exceeds the threshold.
+struct DensityUpdate {
+    float *cache;            // [L][R][R][R], updated in place when density is set
+    const float *density;    // nullable: threshold the cache as it stands
+    float decay, threshold;
+};
+
+__device__ __forceinline__ bool density_bit(const DensityUpdate &u, uint64_t i) {
+    float c = u.cache[i];
+    if (u.density) {
+        const float dc = __fmul_rn(u.decay, c), d = u.density[i];
+        c = d > dc ? d : dc;
+        u.cache[i] = c;
+    }
+    return c > u.threshold;
+}
+
+// changed[0] += voxels whose occupancy changed (a wave's sum, one atomic)
+__device__ __forceinline__ void add_changed(int32_t n, int32_t *changed) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) n += __shfl_xor(n, off, 64);
+    if ((threadIdx.x & 63) == 0 && n != 0) atomicAdd(changed, n);
+}
+
+// dense bitfield from the density cache: one voxel per lane, a wave's 64
+// voxels form two consecutive words
+__global__ void __launch_bounds__(256) density_pack_kernel(DensityUpdate u, uint64_t n_vox,
+                                                          uint32_t *__restrict__ bits, int32_t *__restrict__ changed) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool on = i < n_vox && density_bit(u, i);
+    const uint64_t m = __ballot(on);
+    const int lane = threadIdx.x & 63;
+    int32_t diff = 0;
+    if ((lane == 0 || lane == 32) && i < n_vox) {
+        const uint32_t word = lane == 0 ? (uint32_t)m : (uint32_t)(m >> 32);
+        diff = __popc(word ^ bits[i >> 5]);
+        bits[i >> 5] = word;
+    }
+    add_changed(diff, changed);
+}
+
+// uint8 occupancy from the density cache (for the distance passes)
+__global__ void __launch_bounds__(256) density_bytes_kernel(DensityUpdate u, uint64_t n_vox,
+                                                           const uint32_t *__restrict__ bits, uint8_t *__restrict__ occ,
+                                                           int32_t *__restrict__ changed) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t diff = 0;
+    if (i < n_vox) {
+        const bool on = density_bit(u, i);
+        occ[i] = on ? 1 : 0;
+        diff = on != (((bits[i >> 5] >> (i & 31)) & 1u) != 0);
+    }
+    add_changed(diff, changed);
+}
+
+__global__ void zero_changed_kernel(int32_t *changed) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        changed[0] = 0;
+        changed[1] = 0;
+    }
 }
 
 // ------------------------------------------------------------------ distances
@@ -148,10 +218,97 @@ __device__ __forceinline__ void block_base(const BuildDims &b, int64_t e, int &l
     z0 = rz * b.D + sz * 8;
 }
 
-// one wave per block slot; 4 waves per workgroup
-__global__ void __launch_bounds__(256) classify_kernel(BuildDims b, const uint8_t *__restrict__ occ,
-                                                      int32_t *__restrict__ kind, int32_t *__restrict__ mixed,
-                                                      uint64_t *__restrict__ masks) {
+// Occupancy as bytes of 8 voxels along z, row by row: byte (row, zb) holds
+// voxels z = 8zb .. 8zb+7 of row ((l*R + x)*R + y), bit z & 7, for
+// Rb = ceil(R/8) bytes per row.  One thread per byte, so consecutive threads
+// read consecutive 8-voxel runs (16- or 32-byte loads when the rows allow).
+struct OccSource {        // uint8 occupancy, nonzero = occupied
+    const uint8_t *occ;
+    __device__ __forceinline__ uint8_t byte(uint64_t base, int cnt, bool vec) const {
+        uint8_t v[8];
+        if (vec && cnt == 8) {
+            const uint2 w = *reinterpret_cast<const uint2 *>(occ + base);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                v[j] = (uint8_t)(w.x >> (8 * j));
+                v[4 + j] = (uint8_t)(w.y >> (8 * j));
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = j < cnt ? occ[base + j] : 0;
+        }
+        uint8_t b = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) b |= (uint8_t)((v[j] != 0) << j);
+        return b;
+    }
+};
+
+struct DensitySource {    // density cache, updated and thresholded (DensityUpdate)
+    DensityUpdate u;
+    __device__ __forceinline__ uint8_t byte(uint64_t base, int cnt, bool vec) const {
+        float c[8], d[8];
+        if (vec && cnt == 8) {
+            const float4 c0 = *reinterpret_cast<const float4 *>(u.cache + base);
+            const float4 c1 = *reinterpret_cast<const float4 *>(u.cache + base + 4);
+            c[0] = c0.x; c[1] = c0.y; c[2] = c0.z; c[3] = c0.w;
+            c[4] = c1.x; c[5] = c1.y; c[6] = c1.z; c[7] = c1.w;
+            if (u.density) {
+                const float4 d0 = *reinterpret_cast<const float4 *>(u.density + base);
+                const float4 d1 = *reinterpret_cast<const float4 *>(u.density + base + 4);
+                d[0] = d0.x; d[1] = d0.y; d[2] = d0.z; d[3] = d0.w;
+                d[4] = d1.x; d[5] = d1.y; d[6] = d1.z; d[7] = d1.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                c[j] = j < cnt ? u.cache[base + j] : 0.0f;
+                d[j] = u.density && j < cnt ? u.density[base + j] : 0.0f;
+            }
+        }
+        if (u.density) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float dc = __fmul_rn(u.decay, c[j]);
+                c[j] = d[j] > dc ? d[j] : dc;
+            }
+            if (vec && cnt == 8) {
+                *reinterpret_cast<float4 *>(u.cache + base) = make_float4(c[0], c[1], c[2], c[3]);
+                *reinterpret_cast<float4 *>(u.cache + base + 4) = make_float4(c[4], c[5], c[6], c[7]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if (j < cnt) u.cache[base + j] = c[j];
+            }
+        }
+        uint8_t b = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) b |= (uint8_t)((j < cnt && c[j] > u.threshold) << j);
+        return b;
+    }
+};
+
+template <class Src>
+__global__ void __launch_bounds__(256) row_bits_kernel(Src src, int L, int R, bool vec, uint8_t *__restrict__ rows) {
+    const int Rb = (R + 7) >> 3;
+    const uint64_t n = (uint64_t)L * R * R * Rb;
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const uint64_t row = t / Rb;
+    const int z0 = (int)(t % Rb) * 8;
+    rows[t] = src.byte(row * R + z0, min(8, R - z0), vec);
+}
+
+// One wave per 8^3 block slot (4 per workgroup): the block's leaf words from
+// the row bytes (word x, bit y*8 + z), its kind (0 empty, 1 full, 2 mixed).
+// With changed (a refresh), the words are compared with the previous ones
+// (masks): the block is marked dirty when they differ, changed[0] gains the
+// voxels that flipped, and changed[1] is set when the block's kind changed,
+// which is what forces the tree to be renumbered.
+__global__ void __launch_bounds__(256) block_classify_kernel(BuildDims b, const uint8_t *__restrict__ rowbits,
+                                                            int32_t *__restrict__ kind, int32_t *__restrict__ mixed,
+                                                            uint64_t *__restrict__ masks, int32_t *__restrict__ dirty,
+                                                            int32_t *__restrict__ changed) {
     __shared__ uint8_t rows[4][64];
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int64_t e = (int64_t)blockIdx.x * 4 + wid;
@@ -160,35 +317,45 @@ __global__ void __launch_bounds__(256) classify_kernel(BuildDims b, const uint8_
     if (live) {
         int lev, x0, y0, z0;
         block_base(b, e, lev, x0, y0, z0);
-        int x = x0 + (lane >> 3), y = y0 + (lane & 7);
-        if (x < b.R && y < b.R) {
-            const uint8_t *row = occ + (((size_t)lev * b.R + x) * b.R + y) * b.R;
-            for (int z = 0; z < 8; ++z)
-                if (z0 + z < b.R && row[z0 + z] != 0) byte |= (uint8_t)(1u << z);
-        }
+        const int x = x0 + (lane >> 3), y = y0 + (lane & 7);
+        const int Rb = (b.R + 7) >> 3;
+        if (x < b.R && y < b.R && z0 < b.R) byte = rowbits[(((uint64_t)lev * b.R + x) * b.R + y) * Rb + (z0 >> 3)];
     }
     rows[wid][lane] = byte;
     __syncthreads();
     if (!live) return;
     // word x of the leaf = bytes (x, y=0..7): bit y*8 + z
     uint64_t word = 0;
+    int32_t diff = 0;
     if (lane < 8) {
         for (int y = 0; y < 8; ++y) word |= (uint64_t)rows[wid][lane * 8 + y] << (8 * y);
+        if (changed) diff = __popcll(word ^ masks[e * 8 + lane]);
         masks[e * 8 + lane] = word;
     }
-    bool any_on = __ballot(lane < 8 && word != 0) != 0;
-    bool all_on = __ballot(lane < 8 && word == ~0ull) == 0xffull;
+    const bool any_on = __ballot(lane < 8 && word != 0) != 0;
+    const bool all_on = __ballot(lane < 8 && word == ~0ull) == 0xffull;
+    const int k = all_on ? 1 : (any_on ? 2 : 0);
+    if (changed) {
+        const bool dirt = __ballot(diff != 0) != 0;
+        add_changed(diff, changed);
+        if (lane == 0) {
+            if (k != kind[e]) changed[1] = 1;
+            dirty[e] = dirt;
+        }
+    }
     if (lane == 0) {
-        int k = all_on ? 1 : (any_on ? 2 : 0);
         kind[e] = k;
         mixed[e] = k == 2;
     }
 }
 
-// one workgroup per root cell: empty tile / full tile / node
+// gate (nullable) on the kernels below: nothing is done when *gate is 0 (a
+// refresh that changed no block's kind keeps the tree's numbering).
 __global__ void __launch_bounds__(256) root_kernel(BuildDims b, const int32_t *__restrict__ kind,
-                                                  int32_t *__restrict__ root_kind, int32_t *__restrict__ is_node) {
+                                                  int32_t *__restrict__ root_kind, int32_t *__restrict__ is_node,
+                                                  const int32_t *gate) {
     __shared__ int n_empty, n_full;
+    if (gate && *gate == 0) return;
     if (threadIdx.x == 0) {
         n_empty = 0;
         n_full = 0;
@@ -213,7 +380,8 @@ __global__ void __launch_bounds__(256) root_kernel(BuildDims b, const int32_t *_
 
 __global__ void root_write_kernel(BuildDims b, const int32_t *__restrict__ root_kind,
                                   const int64_t *__restrict__ node_idx, int32_t *__restrict__ root,
-                                  VdbCounts *counts) {
+                                  VdbCounts *counts, const int32_t *gate) {
+    if (gate && *gate == 0) return;
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= b.n_root) return;
     int rk = root_kind[r];
@@ -232,7 +400,8 @@ __global__ void __launch_bounds__(256) node_write_kernel(BuildDims b, const int3
                                                         const int64_t *__restrict__ leaf_idx,
                                                         uint64_t *__restrict__ child, uint64_t *__restrict__ value,
                                                         uint32_t *__restrict__ rank, int32_t *__restrict__ slot,
-                                                        VdbCounts *counts) {
+                                                        VdbCounts *counts, const int32_t *gate) {
+    if (gate && *gate == 0) return;
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int64_t job = (int64_t)blockIdx.x * 4 + wid;
     if (job >= b.n_root * b.W) return;
@@ -285,14 +454,19 @@ __device__ void leaf_uniform_subblocks(const uint64_t *w, uint64_t &u2, uint64_t
     }
 }
 
+// gate (nullable): when *gate is 0 only the leaves of dirty blocks (dirty[e]
+// != 0) are rewritten -- the numbering is unchanged -- else every leaf.
 __global__ void leaf_write_kernel(BuildDims b, const int32_t *__restrict__ mixed, const int64_t *__restrict__ leaf_idx,
                                   const uint64_t *__restrict__ masks, uint64_t *__restrict__ leaves,
-                                  uint64_t *__restrict__ sub, VdbCounts *counts) {
+                                  uint64_t *__restrict__ sub, VdbCounts *counts, const int32_t *gate,
+                                  const int32_t *__restrict__ dirty) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t e = t >> 3;
     int j = (int)(t & 7);
     if (e >= b.n_block) return;
-    if (e == 0 && j == 0) counts->n_leaves = leaf_idx[b.n_block];
+    const bool all = !gate || *gate != 0;
+    if (!all && !dirty[e]) return;
+    if (all && e == 0 && j == 0) counts->n_leaves = leaf_idx[b.n_block];
     if (!mixed[e]) return;
     leaves[leaf_idx[e] * 8 + j] = masks[e * 8 + j];
     if (j == 0) {
@@ -345,7 +519,8 @@ __global__ void geom_kernel(const float *__restrict__ boxes, int L, int R, float
     G[9 + a] = 0.0f;
 }
 
-__global__ void zero_counts_kernel(VdbCounts *c) {
+__global__ void zero_counts_kernel(VdbCounts *c, const int32_t *gate) {
+    if (gate && *gate == 0) return;
     if (threadIdx.x == 0) *c = VdbCounts{0, 0, 0, 0, 0, 0};
 }
 
@@ -368,33 +543,72 @@ struct VdbBuildState {
     int32_t *kind, *mixed, *root_kind, *is_node;
     uint64_t *masks;
     int64_t *leaf_idx, *node_idx, *tiles;
+    uint8_t *rowbits;   // occupancy as row bytes (row_bits_kernel), L*R*R*ceil(R/8)
+    int32_t *dirty;     // per block: its bits changed in the last density refresh
+    int32_t *changed;   // [2] of the last density refresh when the caller passes none
 };
 
 // Classifies every 8^3 block of occ and writes the tree into the grid's
 // storage (sized for the worst case at build time): the kernels of a build,
 // all asynchronous on s.
-hipError_t enqueue_vdb(ogv_grid *g, const VdbBuildState &st, const uint8_t *occ, hipStream_t s) {
+// The tree from the block kinds and masks left by a classification: root
+// kinds, node and leaf numbering, and the node and leaf records.  gate
+// (nullable) as on the kernels: when it reads 0 only dirty leaves are
+// rewritten.
+hipError_t enqueue_tree(ogv_grid *g, const VdbBuildState &st, const int32_t *gate, hipStream_t s) {
     const BuildDims &b = st.b;
     GridView &v = g->view;
-    zero_counts_kernel<<<1, 64, 0, s>>>(g->counts_dev);
-    classify_kernel<<<(unsigned)((b.n_block + 3) / 4), 256, 0, s>>>(b, occ, st.kind, st.mixed, st.masks);
-    root_kernel<<<(unsigned)b.n_root, 256, 0, s>>>(b, st.kind, st.root_kind, st.is_node);
+    root_kernel<<<(unsigned)b.n_root, 256, 0, s>>>(b, st.kind, st.root_kind, st.is_node, gate);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = launch_excl_scan(st.is_node, b.n_root, st.node_idx, st.tiles, 0, nullptr, s);
+    if (e == hipSuccess) e = launch_excl_scan(st.is_node, b.n_root, st.node_idx, st.tiles, 0, nullptr, s, gate);
     if (e == hipSuccess) {
         root_write_kernel<<<(unsigned)((b.n_root + 255) / 256), 256, 0, s>>>(b, st.root_kind, st.node_idx,
-                                                                            (int32_t *)v.root, g->counts_dev);
+                                                                            (int32_t *)v.root, g->counts_dev, gate);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = launch_excl_scan(st.mixed, b.n_block, st.leaf_idx, st.tiles, 0, nullptr, s);
+    if (e == hipSuccess) e = launch_excl_scan(st.mixed, b.n_block, st.leaf_idx, st.tiles, 0, nullptr, s, gate);
     if (e == hipSuccess) {
         node_write_kernel<<<(unsigned)((b.n_root * b.W + 3) / 4), 256, 0, s>>>(
             b, st.root_kind, st.node_idx, st.kind, st.leaf_idx, (uint64_t *)v.child, (uint64_t *)v.value,
-            (uint32_t *)v.rank, (int32_t *)v.slot, g->counts_dev);
+            (uint32_t *)v.rank, (int32_t *)v.slot, g->counts_dev, gate);
         leaf_write_kernel<<<(unsigned)((b.n_block * 8 + 255) / 256), 256, 0, s>>>(
-            b, st.mixed, st.leaf_idx, st.masks, (uint64_t *)v.leaves, (uint64_t *)v.sub, g->counts_dev);
+            b, st.mixed, st.leaf_idx, st.masks, (uint64_t *)v.leaves, (uint64_t *)v.sub, g->counts_dev, gate,
+            st.dirty);
         e = hipGetLastError();
     }
+    return e;
+}
+
+unsigned row_bits_blocks(const BuildDims &b) {
+    return (unsigned)(((uint64_t)b.L * b.R * b.R * ((b.R + 7) / 8) + 255) / 256);
+}
+
+hipError_t enqueue_vdb(ogv_grid *g, const VdbBuildState &st, const uint8_t *occ, hipStream_t s) {
+    const BuildDims &b = st.b;
+    zero_counts_kernel<<<1, 64, 0, s>>>(g->counts_dev, nullptr);
+    const bool vec = b.R % 8 == 0 && (uintptr_t)occ % 8 == 0;   // 8-byte loads stay aligned
+    row_bits_kernel<<<row_bits_blocks(b), 256, 0, s>>>(OccSource{occ}, b.L, b.R, vec, st.rowbits);
+    block_classify_kernel<<<(unsigned)((b.n_block + 3) / 4), 256, 0, s>>>(b, st.rowbits, st.kind, st.mixed, st.masks,
+                                                                         st.dirty, nullptr);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = enqueue_tree(g, st, nullptr, s);
+    return e;
+}
+
+// Refresh from the density cache: classification with the threshold fused in,
+// then the tree rebuilt -- renumbered when a block's kind changed, else only
+// the leaves whose bits changed rewritten (every launch reads changed[1]).
+hipError_t enqueue_vdb_density(ogv_grid *g, const VdbBuildState &st, const DensityUpdate &u, int32_t *changed,
+                               hipStream_t s) {
+    const BuildDims &b = st.b;
+    zero_changed_kernel<<<1, 64, 0, s>>>(changed);
+    const bool vec = b.R % 4 == 0 && ((uintptr_t)u.cache | (uintptr_t)u.density) % 16 == 0;   // 16-byte accesses aligned
+    row_bits_kernel<<<row_bits_blocks(b), 256, 0, s>>>(DensitySource{u}, b.L, b.R, vec, st.rowbits);
+    block_classify_kernel<<<(unsigned)((b.n_block + 3) / 4), 256, 0, s>>>(b, st.rowbits, st.kind, st.mixed, st.masks,
+                                                                         st.dirty, changed);
+    zero_counts_kernel<<<1, 64, 0, s>>>(g->counts_dev, changed + 1);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = enqueue_tree(g, st, changed + 1, s);
     return e;
 }
 
@@ -444,7 +658,7 @@ extern "C" ogv_status ogv_dense_build(int32_t L, int32_t R, const float *boxes, 
     hipError_t e = hipMemcpyAsync((void *)v.boxes, g->boxes_host, sizeof(float) * 6 * L, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
         geom_kernel<<<1, 64, 0, s>>>(v.boxes, L, R, (float *)v.geom);
-        dense_pack_kernel<<<(unsigned)((n_words + 255) / 256), 256, 0, s>>>(occ, n_vox, (uint32_t *)v.bits, n_words);
+        dense_pack_kernel<<<(unsigned)((n_vox + 255) / 256), 256, 0, s>>>(occ, n_vox, (uint32_t *)v.bits);
         e = hipGetLastError();
     }
     // the host copy of the boxes must outlive the async copy
@@ -492,7 +706,7 @@ extern "C" ogv_status ogv_dist_build(int32_t L, int32_t R, const float *boxes, c
     hipError_t e = hipMemcpyAsync((void *)v.boxes, g->boxes_host, sizeof(float) * 6 * L, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
         geom_kernel<<<1, 64, 0, s>>>(v.boxes, L, R, (float *)v.geom);
-        dense_pack_kernel<<<(unsigned)((n_words + 255) / 256), 256, 0, s>>>(occ, n_vox, (uint32_t *)v.bits, n_words);
+        dense_pack_kernel<<<(unsigned)((n_vox + 255) / 256), 256, 0, s>>>(occ, n_vox, (uint32_t *)v.bits);
         enqueue_dist(occ, L, R, (uint8_t *)v.dist, (uint8_t *)g->state, s);
         e = hipGetLastError();
     }
@@ -564,6 +778,9 @@ extern "C" ogv_status ogv_vdb_build(int32_t L, int32_t R, const float *boxes, co
     size_t t_isnode = take(sizeof(int32_t) * b.n_root);
     size_t t_nodeidx = take(sizeof(int64_t) * (b.n_root + 1));
     size_t t_tiles = take(sizeof(int64_t) * (scan_tiles(b.n_block) + 1));
+    size_t t_dirty = take(sizeof(int32_t) * b.n_block);
+    size_t t_rowbits = take((size_t)L * R * R * ((R + 7) / 8));
+    size_t t_changed = take(sizeof(int32_t) * 2);
     size_t scratch_total = off;
 
     ogv_grid *g = new ogv_grid();
@@ -613,6 +830,9 @@ extern "C" ogv_status ogv_vdb_build(int32_t L, int32_t R, const float *boxes, co
     bs->root_kind = (int32_t *)(t + t_rootkind);
     bs->is_node = (int32_t *)(t + t_isnode);
     bs->tiles = (int64_t *)(t + t_tiles);
+    bs->dirty = (int32_t *)(t + t_dirty);
+    bs->rowbits = (uint8_t *)(t + t_rowbits);
+    bs->changed = (int32_t *)(t + t_changed);
 
     hipError_t e = hipMemcpyAsync((void *)v.boxes, g->boxes_host, sizeof(float) * 6 * L, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
@@ -689,8 +909,8 @@ extern "C" ogv_status ogv_grid_refresh(ogv_grid *grid, const uint8_t *occ, void 
     hipStream_t s = (hipStream_t)stream;
     GridView &v = grid->view;
     if (v.kind == 0 || v.kind == 2) {
-        const uint64_t n_vox = (uint64_t)v.L * v.R * v.R * v.R, n_words = (n_vox + 31) / 32;
-        dense_pack_kernel<<<(unsigned)((n_words + 255) / 256), 256, 0, s>>>(occ, n_vox, (uint32_t *)v.bits, n_words);
+        const uint64_t n_vox = (uint64_t)v.L * v.R * v.R * v.R;
+        dense_pack_kernel<<<(unsigned)((n_vox + 255) / 256), 256, 0, s>>>(occ, n_vox, (uint32_t *)v.bits);
         if (v.kind == 2) enqueue_dist(occ, v.L, v.R, (uint8_t *)v.dist, (uint8_t *)grid->state, s);
         OGV_CHECK_LAUNCH();
         grid->build_stream = s;
@@ -700,6 +920,41 @@ extern "C" ogv_status ogv_grid_refresh(ogv_grid *grid, const uint8_t *occ, void 
     const hipError_t e = enqueue_vdb(grid, *(const VdbBuildState *)grid->state, occ, s);
     if (e != hipSuccess) OGV_FAIL(OGV_ERR_HIP, std::string("VDB refresh failed: ") + hipGetErrorString(e));
     grid->counts_ready = false;   // ogv_grid_info_get waits for this stream and re-reads them
+    grid->build_stream = s;
+    return OGV_OK;
+}
+
+extern "C" ogv_status ogv_grid_refresh_density(ogv_grid *grid, float *cache, const float *density, float decay,
+                                               float threshold, int32_t *changed, void *stream) {
+    if (!grid || !cache) OGV_FAIL(OGV_ERR_INVALID, "null argument");
+    if (density && !(decay >= 0.0f && decay <= 1.0f)) OGV_FAIL(OGV_ERR_INVALID, "decay must be in [0, 1]");
+    if (std::isnan(threshold)) OGV_FAIL(OGV_ERR_INVALID, "threshold is NaN");
+    hipStream_t s = (hipStream_t)stream;
+    GridView &v = grid->view;
+    const uint64_t n_vox = (uint64_t)v.L * v.R * v.R * v.R;
+    const DensityUpdate u{cache, density, decay, threshold};
+    const unsigned blocks = (unsigned)((n_vox + 255) / 256);
+    if (v.kind == 0 || v.kind == 2) {
+        int32_t *ch = changed ? changed : (int32_t *)((char *)grid->mem + kDenseChanged);
+        zero_changed_kernel<<<1, 64, 0, s>>>(ch);
+        if (v.kind == 0) {
+            density_pack_kernel<<<blocks, 256, 0, s>>>(u, n_vox, (uint32_t *)v.bits, ch);
+        } else {
+            // thresholded bytes into the pass buffer, then the bitfield and the distances from them
+            uint8_t *tmp = (uint8_t *)grid->state;
+            density_bytes_kernel<<<blocks, 256, 0, s>>>(u, n_vox, v.bits, tmp, ch);
+            dense_pack_kernel<<<(unsigned)((n_vox + 255) / 256), 256, 0, s>>>(tmp, n_vox, (uint32_t *)v.bits);
+            enqueue_dist(tmp, v.L, v.R, (uint8_t *)v.dist, tmp, s);
+        }
+        OGV_CHECK_LAUNCH();
+        grid->build_stream = s;
+        return OGV_OK;
+    }
+    if (!grid->state) OGV_FAIL(OGV_ERR_INVALID, "grid has no build state");
+    const VdbBuildState &st = *(const VdbBuildState *)grid->state;
+    const hipError_t e = enqueue_vdb_density(grid, st, u, changed ? changed : st.changed, s);
+    if (e != hipSuccess) OGV_FAIL(OGV_ERR_HIP, std::string("VDB density refresh failed: ") + hipGetErrorString(e));
+    grid->counts_ready = false;
     grid->build_stream = s;
     return OGV_OK;
 }

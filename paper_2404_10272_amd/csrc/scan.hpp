@@ -43,9 +43,12 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t x, int64_t *lds, int6
     return wbase + incl - x;
 }
 
+// gate (nullable, every kernel here): the kernel does nothing when *gate is 0.
 __global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(const int32_t *__restrict__ counts, int64_t n,
-                                                                  int64_t *__restrict__ tile_sums) {
+                                                                  int64_t *__restrict__ tile_sums,
+                                                                  const int32_t *gate = nullptr) {
     __shared__ int64_t lds[kScanThreads / 64];
+    if (gate && *gate == 0) return;
     int64_t base = (int64_t)blockIdx.x * kScanTile;
     int64_t s = 0;
 #pragma unroll
@@ -62,8 +65,10 @@ __global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(const int32_t
 // total to *total and, when overflow is given, whether it exceeds capacity.
 __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(int64_t *__restrict__ tile_sums, int64_t n_tiles,
                                                                  int64_t *__restrict__ total_out, int64_t capacity,
-                                                                 int32_t *__restrict__ overflow) {
+                                                                 int32_t *__restrict__ overflow,
+                                                                 const int32_t *gate = nullptr) {
     __shared__ int64_t lds[kScanThreads / 64];
+    if (gate && *gate == 0) return;
     int64_t carry = 0;
     for (int64_t base = 0; base < n_tiles; base += kScanThreads) {
         int64_t i = base + threadIdx.x;
@@ -81,8 +86,10 @@ __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(int64_t *__res
 
 __global__ void __launch_bounds__(kScanThreads) scan_apply_kernel(const int32_t *__restrict__ counts, int64_t n,
                                                                  const int64_t *__restrict__ tile_base,
-                                                                 int64_t *__restrict__ offsets) {
+                                                                 int64_t *__restrict__ offsets,
+                                                                 const int32_t *gate = nullptr) {
     __shared__ int64_t lds[kScanThreads / 64];
+    if (gate && *gate == 0) return;
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int32_t c[kScanItems];
     int64_t s = 0;
@@ -111,8 +118,10 @@ __global__ void __launch_bounds__(kScanThreads) scan_apply_direct_kernel(const i
                                                                         const int64_t *__restrict__ tile_sums,
                                                                         int64_t *__restrict__ offsets,
                                                                         int64_t capacity,
-                                                                        int32_t *__restrict__ overflow) {
+                                                                        int32_t *__restrict__ overflow,
+                                                                        const int32_t *gate = nullptr) {
     __shared__ int64_t lds[kScanThreads / 64];
+    if (gate && *gate == 0) return;
     int64_t before = 0;
     for (int64_t k = threadIdx.x; k < (int64_t)blockIdx.x; k += kScanThreads) before += tile_sums[k];
     int64_t tile_base;
@@ -144,17 +153,19 @@ __global__ void __launch_bounds__(kScanThreads) scan_apply_direct_kernel(const i
 // scan_tiles(n) + 1 int64 of scratch.  overflow (nullable) <- total > capacity.
 inline int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
 
+// gate (nullable): device flag; when it reads 0 the launched kernels do
+// nothing (out is left as it was).
 inline hipError_t launch_excl_scan(const int32_t *in, int64_t n, int64_t *out, int64_t *tiles, int64_t capacity,
-                                   int32_t *overflow, hipStream_t s) {
+                                   int32_t *overflow, hipStream_t s, const int32_t *gate = nullptr) {
     int64_t nt = scan_tiles(n);
     if (nt > 0 && nt <= kScanDirectTiles) {
-        scan_reduce_kernel<<<(unsigned)nt, kScanThreads, 0, s>>>(in, n, tiles);
-        scan_apply_direct_kernel<<<(unsigned)nt, kScanThreads, 0, s>>>(in, n, tiles, out, capacity, overflow);
+        scan_reduce_kernel<<<(unsigned)nt, kScanThreads, 0, s>>>(in, n, tiles, gate);
+        scan_apply_direct_kernel<<<(unsigned)nt, kScanThreads, 0, s>>>(in, n, tiles, out, capacity, overflow, gate);
         return hipGetLastError();
     }
-    if (nt > 0) scan_reduce_kernel<<<(unsigned)nt, kScanThreads, 0, s>>>(in, n, tiles);
-    scan_tiles_kernel<<<1, kScanThreads, 0, s>>>(tiles, nt, out + n, capacity, overflow);
-    if (nt > 0) scan_apply_kernel<<<(unsigned)nt, kScanThreads, 0, s>>>(in, n, tiles, out);
+    if (nt > 0) scan_reduce_kernel<<<(unsigned)nt, kScanThreads, 0, s>>>(in, n, tiles, gate);
+    scan_tiles_kernel<<<1, kScanThreads, 0, s>>>(tiles, nt, out + n, capacity, overflow, gate);
+    if (nt > 0) scan_apply_kernel<<<(unsigned)nt, kScanThreads, 0, s>>>(in, n, tiles, out, gate);
     return hipGetLastError();
 }
 

@@ -66,3 +66,117 @@ def test_refresh_rejects_another_shape():
     g = api.build_vdb(torch.from_numpy(w.occ).cuda(), w.boxes, w.ilog2)
     with pytest.raises(api.OgvError):
         g.refresh(torch.zeros((1, 8, 8, 8), dtype=torch.uint8, device="cuda"))
+
+
+def _block_kinds(occ):
+    L, R = occ.shape[0], occ.shape[1]
+    n = occ.reshape(L, R // 8, 8, R // 8, 8, R // 8, 8).sum(axis=(2, 4, 6))
+    return np.where(n == 0, 0, np.where(n == 512, 1, 2))
+
+
+def _density_sequence(w, rng):
+    """16 refreshes of a synthetic training run on the object grid: densities
+    that grow towards a field concentrated on the object, a refresh that
+    changes nothing, one that flips a few voxels inside mixed blocks only (the
+    tree keeps its structure), and one that only moves the threshold.  Yields
+    (density or None, decay, threshold, what)."""
+    shape = w.occ.shape
+    base = np.where(w.occ > 0, rng.uniform(2.0, 20.0, shape), rng.uniform(0.0, 1.2, shape)).astype(np.float32)
+    thr = np.float32(1.0)
+    for k in range(12):
+        scale = np.float32(0.25 + 0.75 * k / 11)
+        noise = np.exp(rng.normal(0.0, 0.4, shape)).astype(np.float32)
+        yield (base * scale * noise).astype(np.float32), np.float32(0.95), thr, f"ramp {k}"
+    yield "same", np.float32(0.5), thr, "unchanged"
+    yield "flip", np.float32(0.0), thr, "flips inside leaves"
+    yield None, np.float32(0.0), np.float32(1.5), "threshold moved"
+    noise = np.exp(rng.normal(0.0, 0.4, shape)).astype(np.float32)
+    yield (base * noise).astype(np.float32), np.float32(0.95), np.float32(1.5), "last"
+
+
+def _flip_inside_leaves(cache, thr, rng, n=200):
+    """A density equal to the cache except n occupied voxels of mixed 8^3
+    blocks, each with at least two occupied voxels, set below the threshold
+    (at most one per block, so every block stays mixed)."""
+    occ = cache > thr
+    kinds = _block_kinds(occ)
+    cnt = occ.reshape(occ.shape[0], 16, 8, 16, 8, 16, 8).sum(axis=(2, 4, 6))
+    cand = np.argwhere((kinds == 2) & (cnt >= 2))
+    pick = cand[rng.choice(len(cand), size=min(n, len(cand)), replace=False)]
+    d = cache.copy()
+    for l, bx, by, bz in pick:
+        blk = occ[l, 8 * bx:8 * bx + 8, 8 * by:8 * by + 8, 8 * bz:8 * bz + 8]
+        i, j, k = np.argwhere(blk)[0]
+        d[l, 8 * bx + i, 8 * by + j, 8 * bz + k] = np.float32(0.0)
+    return d, len(pick)
+
+
+@pytest.mark.parametrize("kind", ["vdb", "dense", "dist"])
+def test_density_refresh_sequence(kind):
+    """ogv_grid_refresh_density over 16 refreshes on the object grid: the
+    cache it leaves equals numpy's max(decay*cache, density) bit for bit, the
+    change counters count the flipped voxels (and, for a VDB, whether a block
+    changed kind), and the grid is the oracle's for the thresholded cache --
+    tree counts, occupancy read back, distances, and the samples of 20,000
+    rays every time and of all 640,000 at the end."""
+    w = scenes.workload("object")
+    rng = np.random.default_rng(7100)
+    pick = np.sort(rng.choice(w.n_rays, size=20000, replace=False))
+    o_h, d_h = np.ascontiguousarray(w.origins[pick]), np.ascontiguousarray(w.dirs[pick])
+    o, d = torch.from_numpy(o_h).cuda(), torch.from_numpy(d_h).cuda()
+    cache = rng.uniform(0.0, 2.0, w.occ.shape).astype(np.float32)
+    thr0 = np.float32(1.0)
+    occ = (cache > thr0).astype(np.uint8)
+    occ_d = torch.from_numpy(occ).cuda()
+    g = {"vdb": lambda: api.build_vdb(occ_d, w.boxes, w.ilog2), "dense": lambda: api.build_dense(occ_d, w.boxes),
+         "dist": lambda: api.build_dist(occ_d, w.boxes)}[kind]()
+    cache_d = torch.from_numpy(cache).cuda()
+    changed = torch.full((2,), -1, dtype=torch.int32, device="cuda")
+    structure_kept = 0
+    for dens, decay, thr, what in _density_sequence(w, rng):
+        if isinstance(dens, str):
+            dens = cache.copy() if dens == "same" else _flip_inside_leaves(cache, thr, rng)[0]
+        prev = occ
+        if dens is not None:
+            dc = (decay * cache).astype(np.float32)
+            cache = np.where(dens > dc, dens, dc).astype(np.float32)
+        occ = (cache > thr).astype(np.uint8)
+        g.refresh_density(cache_d, None if dens is None else torch.from_numpy(dens).cuda(), float(decay), float(thr),
+                          changed)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(cache_d.cpu().numpy(), cache, err_msg=what)
+        n_flip = int(np.count_nonzero(occ != prev))
+        moved = int(kind == "vdb" and bool((_block_kinds(occ) != _block_kinds(prev)).any()))
+        assert changed.cpu().tolist() == [n_flip, moved], what
+        structure_kept += kind == "vdb" and n_flip > 0 and not moved
+        print(what, n_flip, moved, flush=True)
+        np.testing.assert_array_equal(g.to_dense().cpu().numpy(), occ, err_msg=what)
+        if kind == "vdb":
+            st = oracle.Scene(occ, w.boxes).vdb_stats(w.ilog2)
+            info = g.info()
+            assert (info["n_nodes"], info["n_leaves"], info["n_tiles_full"], info["n_tiles_empty"]) == (
+                st["nodes"], st["leaves"], st["slot_full"], st["slot_empty"]), what
+        if kind == "dist":
+            np.testing.assert_array_equal(g.distances().cpu().numpy(), oracle.chessboard_distance(occ), err_msg=what)
+        got = _sample(g, o, d, w)
+        ref = oracle.sample_rays(oracle.Scene(occ, w.boxes), o_h, d_h, w.near, w.far, w.step, "dense_branch")
+        for k in ("offsets", "ray_ids", "t0", "t1"):
+            np.testing.assert_array_equal(got[k], ref[k], err_msg=f"{what} {k}")
+    if kind == "vdb":
+        assert structure_kept >= 1, "no refresh took the path that keeps the tree's numbering"
+    got = _sample(g, torch.from_numpy(w.origins).cuda(), torch.from_numpy(w.dirs).cuda(), w)
+    ref = oracle.sample_rays(oracle.Scene(occ, w.boxes), w.origins, w.dirs, w.near, w.far, w.step, "dense_branch")
+    for k in ("offsets", "ray_ids", "t0", "t1"):
+        np.testing.assert_array_equal(got[k], ref[k], err_msg=f"all rays {k}")
+
+
+def test_density_refresh_rejects_bad_arguments():
+    w = scenes.workload("small")
+    g = api.build_vdb(torch.from_numpy(w.occ).cuda(), w.boxes, w.ilog2)
+    cache = torch.zeros(w.occ.shape, device="cuda")
+    with pytest.raises(api.OgvError):
+        g.refresh_density(cache, cache, decay=1.5)
+    with pytest.raises(api.OgvError):
+        g.refresh_density(cache, threshold=float("nan"))
+    with pytest.raises(api.OgvError):
+        g.refresh_density(torch.zeros((1, 8, 8, 8), device="cuda"))
