@@ -24,6 +24,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "rays/s + samples/s, VDB+HDDA vs dense-OG march, 800×800 rays, sample-exact"
+# comparison samplers on the headline workload: the other loop of the VDB walk,
+# row-major lanes, the dense march (the plain method) in both loops and with
+# row-major lanes, the chessboard-distance march, the VDB walked voxel by voxel
+# in both loops, and the VDB walk with sub-leaf steps
+VARIANTS = ["vdb_other", "vdb_rows", "dense", "dense_skip", "dense_rows", "chessboard", "voxel", "voxel_other",
+            "subleaf"]
 HBM_PEAK_GBS = 8000.0
 
 
@@ -39,6 +45,9 @@ def parse():
     p.add_argument("--no-side", action="store_true", help="skip the composite and batched side measurements")
     p.add_argument("--primary-only", action="store_true",
                    help="time only the headline VDB step (no variant or dense comparisons; for profiling)")
+    p.add_argument("--variants", default=",".join(VARIANTS),
+                   help="comma list of the comparison samplers to time beside the headline (default: all of "
+                        + ", ".join(VARIANTS) + ")")
     p.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                    help="first run a plain device copy of MIB MiB (3 times), to calibrate HBM byte counters")
     return p.parse_args()
@@ -252,6 +261,26 @@ def _median3(fn):
     return sorted(ts)[1], out
 
 
+def hbm_floor(torch, S, steps):
+    """The box's practical HBM rates for the fill's traffic, with torch's own
+    kernels: a write-only fill of three S-element float arrays (the 12 B per
+    sample the expansion writes) and a device-to-device copy of as many bytes
+    (read + write).  The write-only time is the floor under the expansion."""
+    a = [torch.empty(S, dtype=torch.float32, device="cuda") for _ in range(3)]
+
+    def fill():
+        for x in a:
+            x.fill_(1.0)
+
+    fill_ms = time_events(torch, fill, steps, 2)
+    src = torch.ones(3 * S, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    copy_ms = time_events(torch, lambda: dst.copy_(src), steps, 2)
+    B = 12 * S
+    return {"bytes_written": B, "write_only_ms": fill_ms, "write_only_GBps": B / (fill_ms * 1e-3) / 1e9,
+            "copy_ms": copy_ms, "copy_GBps": 2 * B / (copy_ms * 1e-3) / 1e9}
+
+
 def refresh_side(api, torch, scenes, steps):
     """In-place VDB refresh at 128^3 (the object grid) and 256^3 (the same
     grid upsampled twofold): the full re-classify from a uint8 occupancy, and
@@ -398,22 +427,22 @@ def main():
     # in-place asynchronous refresh of the tree (same occupancy, so the grid is unchanged)
     refresh_ms = time_events(torch, lambda: vdb.refresh(occ), 10, 2)
     compare = {}
-    if not args.primary_only:
-        # the other loop variant, row-major lanes, and the dense-grid march
-        hdda_other = Timed(api, torch, vdb, w, o, d, other, W)
-        hdda_rows = Timed(api, torch, vdb, w, o, d, args.variant, 0)
-        plain = Timed(api, torch, dense, w, o, d, "branch", W)
-        plain_skip = Timed(api, torch, dense, w, o, d, "skip", W)
-        plain_rows = Timed(api, torch, dense, w, o, d, "branch", 0)
-        distg = api.build_dist(occ, w.boxes)
-        chess = Timed(api, torch, distg, w, o, d, "branch", W)
-        # the same tree walked one voxel per step ("VDB + DDA", Tab. 1-2)
-        vox = Timed(api, torch, vdb, w, o, d, "voxel_" + args.variant, W)
-        vox_other = Timed(api, torch, vdb, w, o, d, "voxel_" + other, W)
-        # hierarchical steps that also pass uniform sub-blocks inside leaves
-        sub = Timed(api, torch, vdb, w, o, d, "subleaf_" + args.variant, W)
-        assert hdda.S == plain.S == hdda_other.S == plain_skip.S == chess.S == vox.S == vox_other.S == sub.S, \
-            "samplers disagree on the sample count"
+    want = set() if args.primary_only else set(v for v in args.variants.split(",") if v)
+    unknown = want - set(VARIANTS)
+    if unknown:
+        raise SystemExit(f"unknown variants {sorted(unknown)}; choose from {VARIANTS}")
+    if want:
+        distg = api.build_dist(occ, w.boxes) if "chessboard" in want else None
+        # (record name, grid, loop variant, lane layout); every sampler must find the headline's samples
+        spec = {"vdb_other": ("vdb_" + other, vdb, other, W), "vdb_rows": ("vdb_row_major_lanes", vdb, args.variant, 0),
+                "dense": ("dense", dense, "branch", W), "dense_skip": ("dense_skip", dense, "skip", W),
+                "dense_rows": ("dense_row_major_lanes", dense, "branch", 0),
+                "chessboard": ("chessboard", distg, "branch", W),
+                "voxel": ("vdb_voxel_steps", vdb, "voxel_" + args.variant, W),
+                "voxel_other": ("vdb_voxel_steps_" + other, vdb, "voxel_" + other, W),
+                "subleaf": ("vdb_subleaf", vdb, "subleaf_" + args.variant, W)}
+        timed = {v: Timed(api, torch, spec[v][1], w, o, d, spec[v][2], spec[v][3]) for v in VARIANTS if v in want}
+        assert all(t.S == hdda.S for t in timed.values()), "samplers disagree on the sample count"
         N_ = w.n_rays
 
         def rec(t):
@@ -421,18 +450,15 @@ def main():
             return {"ms_per_step": tms, "count_scan_ms": tw + ts, "walk_ms": tw, "fill_ms": tf,
                     "rays_per_s": N_ / (tms * 1e-3)}
 
-        compare["vdb_" + other] = rec(hdda_other)
-        compare["vdb_row_major_lanes"] = rec(hdda_rows)
-        compare["dense"] = dict(rec(plain), bytes=dinfo["bytes"], variant="branch")
-        compare["dense"]["samples_per_s"] = plain.S / (compare["dense"]["ms_per_step"] * 1e-3)
-        compare["dense_skip"] = rec(plain_skip)
-        compare["dense_row_major_lanes"] = rec(plain_rows)
-        # dense bitfield + capped chessboard distances (skips the empty cube around an empty voxel)
-        compare["chessboard"] = dict(rec(chess), bytes=distg.info()["bytes"])
-        compare["vdb_voxel_steps"] = rec(vox)
-        compare["vdb_voxel_steps_" + other] = rec(vox_other)
-        compare["vdb_subleaf"] = rec(sub)
-        compare["speedup_vs_dense"] = compare["dense"]["ms_per_step"] / ms
+        for v, t in timed.items():
+            compare[spec[v][0]] = rec(t)
+        if "dense" in compare:
+            compare["dense"].update(bytes=dinfo["bytes"], variant="branch",
+                                    samples_per_s=timed["dense"].S / (compare["dense"]["ms_per_step"] * 1e-3))
+            compare["speedup_vs_dense"] = compare["dense"]["ms_per_step"] / ms
+        if "chessboard" in compare:
+            compare["chessboard"]["bytes"] = distg.info()["bytes"]
+        del timed
     count_ms = walk_ms + scan_ms
     N, S = w.n_rays, hdda.S
     G = vinfo["bytes"]
@@ -512,6 +538,8 @@ def main():
                      "dominant_kernel": max(kern_ms, key=kern_ms.get),
                      "stages_ms": {"walk": walk_ms, "scan": scan_ms, "fill": fill_ms}},
     }
+    line["hbm_floor"] = hbm_floor(torch, S, min(args.steps, 20))
+    line["hbm_floor"]["fill_vs_write_only"] = line["hbm_floor"]["write_only_ms"] / fill_ms
     line.update(compare)
     if not args.no_side:
         line["composite"] = composite_side(api, torch, scenes, hdda, N, min(args.steps, 20))
