@@ -67,8 +67,10 @@ def copy_calibration(mib):
 
 
 class Timed:
-    """Count + fill of one grid, with an event before count, between count
-    and fill, and after fill, all on the launch stream."""
+    """One sampling pass of one grid: the one-call path (ogv_sample_rays:
+    the walk, then one launch that scans and fills) is the step; the
+    three-call path (count_raw, scan, fill) is timed beside it for the split
+    into walk, scan and fill.  Events on the launch stream."""
 
     def __init__(self, api, torch, grid, w, o, d, variant, image_width=0):
         self.torch = torch
@@ -82,27 +84,32 @@ class Timed:
         self.t1 = torch.empty(self.S, dtype=torch.float32, device="cuda")
 
     def step(self, ev=None):
-        # count = walk (pool reset + count kernel, which also sums the scan
-        # tiles) then scan (one apply launch); fill = expansion (one launch)
+        # one call: walk (pool reset + count kernel, which also sums the scan
+        # tiles and chunks), then the expansion, which scans and fills
         if ev is not None:
             ev[0].record()
-        self.sp.count_raw(self.o, self.d)
+        self.sp.rays(self.o, self.d, self.ids, self.t0, self.t1)
         if ev is not None:
             ev[1].record()
+
+    def step3(self, ev):
+        # three calls: walk, scan (one apply launch), fill (expansion)
+        ev[0].record()
+        self.sp.count_raw(self.o, self.d)
+        ev[1].record()
         self.sp.scan()
-        if ev is not None:
-            ev[2].record()
+        ev[2].record()
         self.sp.fill(self.o, self.d, self.ids, self.t0, self.t1)
-        if ev is not None:
-            ev[3].record()
+        ev[3].record()
 
     def run(self, steps, warmup):
-        """(ms per step, walk ms, scan ms, fill ms), events on the current stream."""
+        """(ms per one-call step, walk ms, scan ms, fill ms of the three-call
+        path), events on the current stream."""
         torch = self.torch
         for _ in range(warmup):
             self.step()
         torch.cuda.synchronize()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
         start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         start.record()
@@ -111,10 +118,21 @@ class Timed:
         end.record()
         torch.cuda.synchronize()
         total_ms = start.elapsed_time(end)
-        stage = [sum(e[i].elapsed_time(e[i + 1]) for e in evs) / steps for i in range(3)]
-        per = sorted(e[0].elapsed_time(e[3]) for e in evs)   # each step alone, first event to last
+        per = sorted(e[0].elapsed_time(e[1]) for e in evs)   # each step alone
         self.step_stats = {"median_ms": per[len(per) // 2], "min_ms": per[0],
                            "p90_ms": per[min(len(per) - 1, (9 * len(per)) // 10)]}
+        for _ in range(warmup):
+            self.step3([torch.cuda.Event(enable_timing=True) for _ in range(4)])
+        torch.cuda.synchronize()
+        ev3 = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for k in range(steps):
+            self.step3(ev3[k])
+        b.record()
+        torch.cuda.synchronize()
+        self.three_call_ms = a.elapsed_time(b) / steps
+        stage = [sum(e[i].elapsed_time(e[i + 1]) for e in ev3) / steps for i in range(3)]
         return total_ms / steps, stage[0], stage[1], stage[2]
 
 
@@ -168,7 +186,8 @@ def cascades_side(api, torch, scenes, steps, warmup):
         ms, walk, scan, fill = t.run(steps, warmup)
         N, S, G = w.n_rays, t.S, grid.info()["bytes"]
         step_bytes = 24 * N + 8 * (N + 1) + 12 * S + G   # the call's inputs and outputs, as for the headline
-        out[name] = {"ms_per_step": ms, "walk_ms": walk, "scan_ms": scan, "fill_ms": fill,
+        out[name] = {"ms_per_step": ms, "walk_ms": walk, "scan_fill_ms": ms - walk,
+                     "three_call": {"ms_per_step": t.three_call_ms, "scan_ms": scan, "fill_ms": fill},
                      "rays_per_s": N / (ms * 1e-3), "samples_per_s": S / (ms * 1e-3), "samples": S,
                      "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del t
@@ -447,8 +466,8 @@ def main():
 
         def rec(t):
             tms, tw, ts, tf = t.run(args.steps, args.warmup)
-            return {"ms_per_step": tms, "count_scan_ms": tw + ts, "walk_ms": tw, "fill_ms": tf,
-                    "rays_per_s": N_ / (tms * 1e-3)}
+            return {"ms_per_step": tms, "walk_ms": tw, "scan_fill_ms": tms - tw, "rays_per_s": N_ / (tms * 1e-3),
+                    "three_call": {"ms_per_step": t.three_call_ms, "scan_ms": ts, "fill_ms": tf}}
 
         for v, t in timed.items():
             compare[spec[v][0]] = rec(t)
@@ -472,12 +491,16 @@ def main():
     # the grid, the expansion writes offsets-indexed samples (and reads the
     # offsets); the scan moves only workspace.
     step_bytes = 24 * N + 8 * (N + 1) + 12 * S + G
-    kern_bytes = {"count_kernel": 24 * N + G, "scan": 0, "expand_kernel": 12 * S + 8 * (N + 1)}
-    kern_ms = {"count_kernel": walk_ms, "scan": scan_ms, "expand_kernel": fill_ms}
+    # the step's two launches (after the pool reset): the walk, and the
+    # expansion that scans and fills; its time is the step's less the walk's
+    scan_fill_ms = ms - walk_ms
+    kern_bytes = {"count_kernel": 24 * N + G, "expand_kernel": 12 * S + 8 * (N + 1)}
+    kern_ms = {"count_kernel": walk_ms, "expand_kernel": scan_fill_ms}
     # workspace traffic the two-pass design adds (not algorithmic): per-ray
-    # counts, run counts and chain heads, 8 B per kept run, the scan's reads
-    ws_bytes = {"count_kernel": 12 * N + 8 * runs, "scan": 4 * N, "expand_kernel": 4 * N + 8 * runs}
-    sum_ms = walk_ms + scan_ms + fill_ms
+    # counts, run counts and chain heads, 8 B per kept run (written, merged,
+    # read back), the counts and sums the expansion's scan reads
+    ws_bytes = {"count_kernel": 12 * N + 16 * runs, "expand_kernel": 8 * N + 8 * runs}
+    sum_ms = ms
     achieved = step_bytes / (sum_ms * 1e-3) / 1e9
 
     counters = None
@@ -495,8 +518,7 @@ def main():
         per_kernel[k] = {"algorithmic_bytes": b, "avg_ms": t, "achieved_GBps": b / (t * 1e-3) / 1e9,
                          "frac": b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, "workspace_bytes": ws_bytes[k]}
         if counters is not None:
-            names = ["scan_apply_direct_kernel", "scan_reduce_kernel"] if k == "scan" else \
-                ["count_kernel", "pool_reset_kernel"] if k == "count_kernel" else [k]
+            names = ["count_kernel", "pool_reset_kernel"] if k == "count_kernel" else [k]
             tr = sum(counters.get(n, 0.0) for n in names)
             per_kernel[k]["traffic"] = tr
             per_kernel[k]["traffic_over_algorithmic"] = tr / b if b else None
@@ -523,23 +545,26 @@ def main():
         "paper_context": "end-to-end FPS with trained Instant-NGP fields on 1x NVIDIA A100, no sampler-only figure: "
                          "VDB + HDDA +12% over NerfAcc on NeRF-Synthetic (Tab. 1), +4% on Mip-NeRF 360 (Tab. 2); "
                          "context, not comparable (vs_baseline is null)",
-        "vdb": {"ms_per_step": ms, "count_scan_ms": count_ms, "walk_ms": walk_ms, "scan_ms": scan_ms,
-                "fill_ms": fill_ms, "rays_per_s": N / (ms * 1e-3),
+        "vdb": {"ms_per_step": ms, "walk_ms": walk_ms, "scan_fill_ms": scan_fill_ms,
+                "three_call": {"ms_per_step": hdda.three_call_ms, "walk_ms": walk_ms, "scan_ms": scan_ms,
+                               "fill_ms": fill_ms, "count_scan_ms": count_ms},
+                "rays_per_s": N / (ms * 1e-3),
                 "bytes": G, "leaves": vinfo["n_leaves"], "build_ms": build_ms, "refresh_ms": refresh_ms,
                 "step_stats": hdda.step_stats},
         "step_bytes": step_bytes,
         "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "runs": runs,
-        "roofline": {"bound": "hbm", "kernel": "sampling call: count_kernel + scan + expand_kernel",
+        "roofline": {"bound": "hbm", "kernel": "sampling call (ogv_sample_rays): count_kernel, then expand_kernel "
+                                               "with the scan inside",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes": step_bytes,
                      "algorithmic_bytes_formula": "24N + 8(N+1) + 12S + G",
                      "avg_ms": sum_ms, "per_kernel": per_kernel,
                      "dominant_kernel": max(kern_ms, key=kern_ms.get),
-                     "stages_ms": {"walk": walk_ms, "scan": scan_ms, "fill": fill_ms}},
+                     "stages_ms": {"walk": walk_ms, "scan_and_fill": scan_fill_ms}},
     }
     line["hbm_floor"] = hbm_floor(torch, S, min(args.steps, 20))
-    line["hbm_floor"]["fill_vs_write_only"] = line["hbm_floor"]["write_only_ms"] / fill_ms
+    line["hbm_floor"]["fill_vs_write_only"] = line["hbm_floor"]["write_only_ms"] / scan_fill_ms
     line.update(compare)
     if not args.no_side:
         line["composite"] = composite_side(api, torch, scenes, hdda, N, min(args.steps, 20))

@@ -142,8 +142,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kEx
                                                               const SceneDesc *__restrict__ scenes,
                                                               const int32_t *__restrict__ lost,
                                                               const int32_t *__restrict__ n_lost) {
-    expand_block(offsets, n_total, nruns, rd, SceneLattices{lats, first, n_scenes}, capacity, ray_ids, t0, t1,
-                 vec4 != 0);
+    // the offsets are read only (no scan inside the expansion)
+    expand_block(const_cast<int64_t *>(offsets), ChunkScan{}, n_total, nruns, rd, SceneLattices{lats, first, n_scenes},
+                 capacity, ray_ids, t0, t1, vec4 != 0);
     batch_fill_lost<kSkip>(scenes, n_scenes, lost, n_lost, offsets, capacity, ray_ids, t0, t1);
 }
 

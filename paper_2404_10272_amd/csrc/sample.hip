@@ -26,12 +26,15 @@ namespace ogv {
 // ------------------------------------------------------------------ kernels
 
 
-// The wave adds its rays' counts to the sums of the scan tiles (kScanTile
-// consecutive rays each) it touches: one wave reduction and one atomic per
-// tile, so the scan needs no reduce launch of its own.
-__device__ __forceinline__ void add_tile_sums(int64_t ray, int32_t n, int64_t *__restrict__ tile_sums) {
+// The wave adds its rays' counts to the sums of the groups of 2^kShift
+// consecutive rays it touches: one wave reduction and one atomic per group.
+// Groups of kScanTile rays are the scan tiles (so the scan needs no reduce
+// launch of its own); groups of kBlock rays are the expansion's chunks (so a
+// one-call pass needs no scan launch at all).
+template <int kShift>
+__device__ __forceinline__ void add_group_sums(int64_t ray, int32_t n, int64_t *__restrict__ tile_sums) {
     const int lane = threadIdx.x & 63;
-    const int32_t key = ray >= 0 ? (int32_t)(ray / kScanTile) : -1;
+    const int32_t key = ray >= 0 ? (int32_t)(ray >> kShift) : -1;
     uint64_t todo = __ballot(key >= 0);
     while (todo) {
         const int leader = __ffsll((unsigned long long)todo) - 1;
@@ -45,6 +48,25 @@ __device__ __forceinline__ void add_tile_sums(int64_t ray, int32_t n, int64_t *_
     }
 }
 
+// The chunk sums (kBlock consecutive rays each).  Every 8 consecutive lanes
+// walk consecutive rays (a pixel row of a tile, or 8 of a row-major range),
+// so their chunks form at most two contiguous segments: a segmented scan over
+// the 8 lanes leaves each segment's total in its last lane, which adds it.
+__device__ __forceinline__ void add_chunk_sums(int64_t ray, int32_t n, int64_t *__restrict__ chunk_sums) {
+    const int32_t key = ray >= 0 ? (int32_t)(ray / kBlock) : -1;
+    const int l8 = threadIdx.x & 7;
+    int32_t v = n;
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+        const int32_t y = __shfl_up(v, off, 8);
+        const int32_t ky = __shfl_up(key, off, 8);
+        if (l8 >= off && ky == key) v += y;
+    }
+    const int32_t kn = __shfl_down(key, 1, 8);
+    const bool last = l8 == 7 || kn != key;
+    if (last && key >= 0 && v != 0) atomicAdd((unsigned long long *)&chunk_sums[key], (unsigned long long)(int64_t)v);
+}
+
 // counts[i] = samples of ray i; nruns[i] = its occupied runs (kRunsLost: the
 // run pool ran dry, the traversal fill writes the ray); the runs themselves
 // go to the pool's slots and chunks; tile_sums[k] gains the counts of rays
@@ -54,7 +76,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kGr
                                                        const float *__restrict__ dirs, int64_t n_rays, Lattice lat,
                                                        int32_t *__restrict__ counts, int32_t *__restrict__ nruns,
                                                        RunPool pool, int image_width,
-                                                       int64_t *__restrict__ tile_sums) {
+                                                       int64_t *__restrict__ tile_sums,
+                                                       int64_t *__restrict__ chunk_sums) {
     extern __shared__ __align__(16) uint32_t smem[];
     Tree tree = reads_tree(kGrid) ? load_tree<kLds>(g, smem) : Tree{};
     const int64_t i = ray_of_thread((int64_t)blockIdx.x * kBlock + threadIdx.x, n_rays, image_width);
@@ -70,7 +93,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kGr
         counts[i] = n;
         nruns[i] = vis.nr;
     }
-    add_tile_sums(i, n, tile_sums);
+    static_assert(kScanTile == 1 << 12 && kBlock == 1 << 8, "group sums assume 4096-ray tiles, 256-ray chunks");
+    add_group_sums<12>(i, n, tile_sums);
+    add_chunk_sums(i, n, chunk_sums);
 }
 
 // Traversal fill: re-walks every ray and writes its samples from offsets[i]
@@ -98,14 +123,17 @@ __global__ void __launch_bounds__(kBlock) fill_kernel(GridView g, const float *_
 }
 
 // zeroes the pool head and the lost-ray count (head[0], head[1]) and the
-// scan tile sums the count pass accumulates
-__global__ void pool_reset_kernel(int32_t *head, int64_t *tile_sums, int64_t n_tiles) {
+// scan tile and chunk sums the count pass accumulates
+__global__ void pool_reset_kernel(int32_t *head, int64_t *tile_sums, int64_t n_tiles, int64_t *chunk_sums,
+                                  int64_t n_chunks) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         head[0] = 0;
         head[1] = 0;
     }
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_tiles; k += (int64_t)gridDim.x * blockDim.x)
         tile_sums[k] = 0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_chunks; k += (int64_t)gridDim.x * blockDim.x)
+        chunk_sums[k] = 0;
 }
 
 // Expansion of the kept runs, then, in the same launch, the traversal fill
@@ -113,23 +141,27 @@ __global__ void pool_reset_kernel(int32_t *head, int64_t *tile_sums, int64_t n_t
 // blocks stride through their list, reading the tree from global memory.
 // Those outputs are disjoint from the expansion's (it skips them, and a
 // 16-byte group they share is written with 4-byte stores).
-template <int kGrid, bool kSkip>
+// kScan: the offsets are not given but written here (ChunkScan), from the
+// count pass's counts and group sums: a one-call pass then needs no scan
+// launch.  The lost rays' first outputs then come from the sums too (the
+// offsets array is being written by other blocks of the same launch).
+template <int kGrid, bool kSkip, bool kScan>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kExpandWaves))) expand_kernel(GridView g, const float *__restrict__ origins,
                                                         const float *__restrict__ dirs,
-                                                        const int64_t *__restrict__ offsets, int64_t n_rays,
+                                                        int64_t *__restrict__ offsets, ChunkScan cs, int64_t n_rays,
                                                         const int32_t *__restrict__ nruns, RunReader rd, Lattice lat,
                                                         int64_t capacity, int32_t *__restrict__ ray_ids,
                                                         float *__restrict__ t0, float *__restrict__ t1, int vec4,
                                                         const int32_t *__restrict__ lost,
                                                         const int32_t *__restrict__ n_lost) {
-    expand_block(offsets, n_rays, nruns, rd, OneLattice{lat}, capacity, ray_ids, t0, t1, vec4 != 0);
+    expand_block<kScan>(offsets, cs, n_rays, nruns, rd, OneLattice{lat}, capacity, ray_ids, t0, t1, vec4 != 0);
     const int64_t m = *n_lost;
     if (m == 0) return;
     const Tree tree = reads_tree(kGrid) ? load_tree<false>(g, nullptr) : Tree{};
     const FillCtx ctx{lat, capacity, ray_ids, t0, t1, nullptr, g.R};
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < m; k += (int64_t)gridDim.x * kBlock) {
         const int64_t i = lost[k];
-        const int64_t first = offsets[i];
+        const int64_t first = kScan ? offset_of_ray(i, cs) : offsets[i];
         if (first >= capacity) continue;
         float o[3], d[3];
         load_ray(origins, dirs, i, o, d);
@@ -302,7 +334,8 @@ namespace {
 
 struct Plan {
     int64_t n_rays;
-    size_t off_counts, off_nruns, off_runs, off_next, off_chunks, off_cnext, off_lost, off_tiles, off_tab, off_ntab, off_thdr,
+    size_t off_counts, off_nruns, off_runs, off_next, off_chunks, off_cnext, off_lost, off_tiles, off_csums, off_tab,
+        off_ntab, off_thdr,
         total;
     int32_t pool_cap;
     int64_t n_tiles;
@@ -332,6 +365,7 @@ bool make_plan(int64_t n_rays, float near_t, float far_t, const ogv_step *step, 
     p->off_cnext = take(sizeof(int32_t) * (size_t)p->pool_cap);
     p->off_lost = take(sizeof(int32_t) * (size_t)n_rays);
     p->off_tiles = take(sizeof(int64_t) * (size_t)(p->n_tiles + 1));
+    p->off_csums = take(sizeof(int64_t) * (size_t)((n_rays + kBlock - 1) / kBlock));
     p->off_tab = take(sizeof(float) * (size_t)p->tab_cap);
     p->off_ntab = take(sizeof(int32_t) * 4);
     p->off_thdr = take(sizeof(TableHeader));
@@ -361,6 +395,7 @@ struct Bufs {
     int32_t *counts, *nruns;
     RunPool pool;
     int64_t *tiles;
+    int64_t *csums;   // per 256-ray chunk
 };
 
 Bufs bufs_of(void *ws, const Plan &p) {
@@ -379,6 +414,7 @@ Bufs bufs_of(void *ws, const Plan &p) {
     b.pool.lost = (int32_t *)(w + p.off_lost);
     b.pool.n_lost = (int32_t *)(w + p.off_ntab) + 2;
     b.tiles = (int64_t *)(w + p.off_tiles);
+    b.csums = (int64_t *)(w + p.off_csums);
     return b;
 }
 
@@ -391,14 +427,15 @@ void launch_count(const GridView &g, const float *o, const float *d, int64_t n, 
                   int width, hipStream_t s) {
     unsigned blocks = (unsigned)((tiled_threads(n, width) + kBlock - 1) / kBlock);
     size_t shm = kLds ? lds_bytes(g) : 0;
-    const int64_t nt = scan_tiles(n);
-    pool_reset_kernel<<<(unsigned)std::min<int64_t>((nt + 255) / 256 + 1, 64), 256, 0, s>>>(b.pool.head, b.tiles, nt);
+    const int64_t nt = scan_tiles(n), nc = (n + kBlock - 1) / kBlock;
+    pool_reset_kernel<<<(unsigned)std::min<int64_t>((nc + 255) / 256 + 1, 64), 256, 0, s>>>(b.pool.head, b.tiles, nt,
+                                                                                         b.csums, nc);
     if (g.L == 1)
         count_kernel<kGrid, kSkip, kLds, true>
-            <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool, width, b.tiles);
+            <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool, width, b.tiles, b.csums);
     else
         count_kernel<kGrid, kSkip, kLds, false>
-            <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool, width, b.tiles);
+            <<<blocks, kBlock, shm, s>>>(g, o, d, n, lat, b.counts, b.nruns, b.pool, width, b.tiles, b.csums);
 }
 
 template <int kGrid, bool kSkip, bool kLds>
@@ -515,8 +552,35 @@ ogv_status fill_all(const ogv_grid *grid, int32_t variant, const float *o, const
     // the expansion's lost-ray walk reads the tree from global memory (the
     // LDS flag is ignored)
 #define OGV_LAUNCH(V, K, L)                                                                                          \
-    expand_kernel<V, K><<<blocks, kBlock, 0, s>>>(g, o, d, offsets, n, b.nruns, reader_of(b), lat, cap, ids, t0, t1, \
-                                                   vec4, b.pool.lost, b.pool.n_lost)
+    expand_kernel<V, K, false><<<blocks, kBlock, 0, s>>>(g, o, d, const_cast<int64_t *>(offsets), ChunkScan{}, n,    \
+                                                          b.nruns, reader_of(b), lat, cap, ids, t0, t1, vec4,        \
+                                                          b.pool.lost, b.pool.n_lost)
+    OGV_DISPATCH(g, variant);
+#undef OGV_LAUNCH
+    OGV_CHECK_LAUNCH();
+    return OGV_OK;
+}
+
+// Rays a one-call pass scans inside the expansion: each expansion block sums
+// the tile sums before its chunk.  That prologue delays its stores; against a
+// separate scan launch it pays up to about 200 tiles (measured: the
+// 640,000-ray object workload, 157 tiles, 0.271 -> 0.264 ms a step; the
+// 1,064,960-ray cascades, 260 tiles, 0.503 -> 0.510 ms).
+constexpr int64_t kScanInExpandTiles = 192;
+
+// scan and fill of a one-call pass in one launch: the expansion writes the
+// offsets (and the overflow flag) itself from the count pass's sums
+ogv_status scan_fill_fused(const ogv_grid *grid, int32_t variant, const float *o, const float *d, int64_t n,
+                           const Lattice &lat, int64_t *offsets, int64_t cap, int32_t *ids, float *t0, float *t1,
+                           int32_t *overflow, void *ws, const Plan &p, hipStream_t s) {
+    Bufs b = bufs_of(ws, p);
+    const unsigned blocks = (unsigned)min(expand_items(n), (int64_t)INT32_MAX);
+    const int vec4 = (((uintptr_t)ids | (uintptr_t)t0 | (uintptr_t)t1) & 15) == 0;
+    const GridView &g = grid->view;
+    const ChunkScan cs{b.counts, b.tiles, b.csums, overflow};
+#define OGV_LAUNCH(V, K, L)                                                                                          \
+    expand_kernel<V, K, true><<<blocks, kBlock, 0, s>>>(g, o, d, offsets, cs, n, b.nruns, reader_of(b), lat, cap,    \
+                                                         ids, t0, t1, vec4, b.pool.lost, b.pool.n_lost)
     OGV_DISPATCH(g, variant);
 #undef OGV_LAUNCH
     OGV_CHECK_LAUNCH();
@@ -644,6 +708,13 @@ extern "C" ogv_status ogv_sample_rays(const ogv_grid *grid, const ogv_sample_opt
     hipStream_t s = (hipStream_t)stream;
     if ((st = build_table(near_t, far_t, step, ws, p, s)) != OGV_OK) return st;
     Lattice lat = make_lattice(near_t, far_t, step, ws, p);
+    if (n > 0 && !vox && p.n_tiles <= kScanInExpandTiles) {
+        // walk, then one launch that scans and fills
+        dispatch_count(grid->view, opts.variant, o, d, n, lat, bufs_of(ws, p), opts.image_width, s);
+        OGV_CHECK_LAUNCH();
+        return scan_fill_fused(grid, opts.variant, o, d, n, lat, offsets, capacity, ray_ids, t0, t1, overflow, ws, p,
+                               s);
+    }
     if ((st = count_and_scan(grid, opts.variant, opts.image_width, o, d, n, lat, offsets, ws, p, capacity, overflow,
                              s)) != OGV_OK)
         return st;

@@ -19,6 +19,7 @@
 
 #include "geometry.hpp"
 #include "internal.hpp"
+#include "scan.hpp"
 
 namespace ogv {
 
@@ -859,6 +860,60 @@ __device__ __forceinline__ int64_t block_incl_scan256(int64_t x, int64_t *lds, i
     return base + x;   // inclusive
 }
 
+// The scan done inside the expansion (one-call sampling): every block derives
+// its 256-ray chunk's offsets from the count pass's per-ray counts and its
+// sums per 4096-ray scan tile and per 256-ray chunk, and the first part of
+// every chunk writes them to the offsets array (the last chunk also the total
+// and the overflow flag).  counts == nullptr: the offsets array is read.
+constexpr int kChunksPerTile = kScanTile / kBlock;
+struct ChunkScan {
+    const int32_t *counts;       // [n_rays]
+    const int64_t *tile_sums;    // [ceil(n_rays / kScanTile)]
+    const int64_t *chunk_sums;   // [ceil(n_rays / kBlock)]
+    int32_t *overflow;           // nullable: set to (total > capacity)
+};
+
+// First output of ray i from the sums (for the rare rays the count pass could
+// not keep runs for; a plain sequential sum).
+__device__ inline int64_t offset_of_ray(int64_t i, const ChunkScan &cs) {
+    const int64_t c = i / kBlock, T = i / kScanTile;
+    int64_t s = 0;
+    for (int64_t k = 0; k < T; ++k) s += cs.tile_sums[k];
+    for (int64_t j = T * kChunksPerTile; j < c; ++j) s += cs.chunk_sums[j];
+    for (int64_t r = c * kBlock; r < i; ++r) s += cs.counts[r];
+    return s;
+}
+
+// Inclusive block scan of x (returned, with its total) and the block sum of
+// y, sharing one exchange through LDS (lds holds 2 * kBlock / 64 entries).
+__device__ __forceinline__ int64_t block_scan_and_sum256(int64_t x, int64_t y, int64_t *lds, int64_t &x_total,
+                                                        int64_t &y_total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t a = __shfl_up(x, off, 64);
+        if (lane >= off) x += a;
+        y += __shfl_xor(y, off, 64);
+    }
+    if (lane == 63) {
+        lds[wid] = x;
+        lds[kBlock / 64 + wid] = y;
+    }
+    __syncthreads();
+    int64_t below = 0;
+    x_total = 0;
+    y_total = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        const int64_t v = lds[w];
+        if (w < wid) below += v;
+        x_total += v;
+        y_total += lds[kBlock / 64 + w];
+    }
+    __syncthreads();
+    return below + x;
+}
+
 // LDS of one expansion block, declared once per kernel so that the two
 // instantiations of expand_chunk share it.
 struct ExpandLds {
@@ -868,16 +923,16 @@ struct ExpandLds {
     int16_t scene[kExpandRuns];
     uint32_t own[kOwnSlots];           // 1 + owner run of each group of the window, at own_slot(group)
     uint32_t wmax[kBlock / 64];
-    int64_t wave[kBlock / 64];
+    int64_t wave[2 * (kBlock / 64)];
 };
 
 // kCone: some ray is on a growing-step lattice, whose points come from a table
 // in global memory.  Otherwise the write loop issues no load: a load there
 // would make every group wait for the stores of the one before (one counter
 // covers both on this architecture).
-template <bool kCone, class Lats>
+template <bool kCone, bool kScan, class Lats>
 __device__ __forceinline__ void expand_chunk(ExpandLds &sh, const float2 *s_lat, int64_t r0, int part,
-                                             const int64_t *__restrict__ offsets, int64_t n_rays,
+                                             int64_t *__restrict__ offsets, const ChunkScan &cs, int64_t n_rays,
                                              const int32_t *__restrict__ nruns, const RunReader &rd,
                                              const Lats &lats, int64_t capacity, int32_t *__restrict__ ray_ids,
                                              float *__restrict__ t0, float *__restrict__ t1, bool vec4) {
@@ -888,10 +943,49 @@ __device__ __forceinline__ void expand_chunk(ExpandLds &sh, const float2 *s_lat,
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t r = r0 + threadIdx.x;
     const bool in = r < n_rays;
-    // The chunk's bounds first (uniform loads): a part with no window of the
-    // chunk returns before it reads anything per ray.
-    const int64_t base = offsets[r0];
-    const int64_t bend = offsets[min(r0 + kBlock, n_rays)];
+    const int64_t rc = in ? r : n_rays - 1;   // lanes past the last ray load a valid one's
+    int64_t base, bend, off, off_next;
+    int nr_rc;
+    int2 slot0, slot1;
+    if constexpr (kScan) {
+        // every load here depends on r alone and is issued in one round: the
+        // sums before the chunk (whole tiles, then the earlier chunks of its
+        // tile), the ray's count, run count and first two run slots (read
+        // whether or not the ray has them; the slot arrays have a column for
+        // every ray)
+        const int64_t c = r0 / kBlock, T = r0 / kScanTile;
+        if (part > 0) {
+            // the chunk's outputs span at most (count + 6) / 4 groups, wherever
+            // they start: a part beyond them has no window (and part 0, which
+            // writes the chunk's offsets, always goes on)
+            if ((cs.chunk_sums[c] + 6) / 4 <= (int64_t)part * kExpandGroups) return;
+        }
+        nr_rc = nruns[rc];
+        slot0 = rd.slots[rc];
+        slot1 = rd.slots[rd.stride + rc];
+        int64_t before = 0;
+        for (int64_t k = threadIdx.x; k < T; k += kBlock) before += cs.tile_sums[k];
+        const int64_t j = T * kChunksPerTile + threadIdx.x;
+        if (j < c) before += cs.chunk_sums[j];
+        const int64_t cnt = in ? (int64_t)cs.counts[r] : 0;
+        int64_t total;
+        const int64_t incl = block_scan_and_sum256(cnt, before, s_wave, total, base);
+        off = base + incl - cnt;
+        off_next = base + incl;
+        bend = base + total;
+        if (part == 0) {
+            if (in) offsets[r] = off;
+            if (r0 + kBlock >= n_rays && threadIdx.x == 0) {
+                offsets[n_rays] = bend;
+                if (cs.overflow) *cs.overflow = bend > capacity ? 1 : 0;
+            }
+        }
+    } else {
+        // the chunk's bounds first (uniform loads): a part with no window of
+        // the chunk returns before it reads anything per ray
+        base = offsets[r0];
+        bend = offsets[min(r0 + kBlock, n_rays)];
+    }
     const int64_t lim = min(bend, capacity);
     if (lim <= base) return;   // block-uniform: nothing to write
     const int64_t G0 = base >> 2;   // the chunk's first group; windows count from it
@@ -900,11 +994,14 @@ __device__ __forceinline__ void expand_chunk(ExpandLds &sh, const float2 *s_lat,
     // them are issued here together: one memory round trip (the ray's offsets
     // and run count, and its first two run slots, read whether or not the ray
     // has them; the slot arrays have a column for every ray).
-    const int64_t rc = in ? r : n_rays - 1;   // lanes past the last ray load a valid one's
-    const int64_t off = offsets[rc], off_next = offsets[rc + 1];
-    const int nr_rc = nruns[rc];
+    if constexpr (!kScan) {
+        off = offsets[rc];
+        off_next = offsets[rc + 1];
+        nr_rc = nruns[rc];
+        slot0 = rd.slots[rc];
+        slot1 = rd.slots[rd.stride + rc];
+    }
     const int nr_raw = in ? nr_rc : 0;
-    const int2 slot0 = rd.slots[rc], slot1 = rd.slots[rd.stride + rc];
     const uint32_t end_rel = (uint32_t)(bend - base);
     const uint32_t lim_rel = (uint32_t)(min(bend, capacity) - base);
     int nr = nr_raw, scene = 0;
@@ -1055,8 +1152,8 @@ __host__ __device__ inline int64_t expand_items(int64_t n_rays) {
     return (n_rays + kBlock - 1) / kBlock * kExpandParts;
 }
 
-template <class Lats>
-__device__ __forceinline__ void expand_block(const int64_t *__restrict__ offsets, int64_t n_rays,
+template <bool kScan = false, class Lats>
+__device__ __forceinline__ void expand_block(int64_t *__restrict__ offsets, const ChunkScan &cs, int64_t n_rays,
                                              const int32_t *__restrict__ nruns, const RunReader &rd,
                                              const Lats &lats, int64_t capacity, int32_t *__restrict__ ray_ids,
                                              float *__restrict__ t0, float *__restrict__ t1, bool vec4) {
@@ -1077,12 +1174,12 @@ __device__ __forceinline__ void expand_block(const int64_t *__restrict__ offsets
     const int64_t chunks = (n_rays + kBlock - 1) / kBlock;
     if (cone) {
         for (int64_t it = blockIdx.x; it < chunks * kExpandParts; it += gridDim.x)
-            expand_chunk<true>(sh, s_lat, it % chunks * kBlock, (int)(it / chunks), offsets, n_rays, nruns, rd, lats,
-                               capacity, ray_ids, t0, t1, vec4);
+            expand_chunk<true, kScan>(sh, s_lat, it % chunks * kBlock, (int)(it / chunks), offsets, cs, n_rays, nruns,
+                                      rd, lats, capacity, ray_ids, t0, t1, vec4);
     } else {
         for (int64_t it = blockIdx.x; it < chunks * kExpandParts; it += gridDim.x)
-            expand_chunk<false>(sh, s_lat, it % chunks * kBlock, (int)(it / chunks), offsets, n_rays, nruns, rd, lats,
-                                capacity, ray_ids, t0, t1, vec4);
+            expand_chunk<false, kScan>(sh, s_lat, it % chunks * kBlock, (int)(it / chunks), offsets, cs, n_rays,
+                                       nruns, rd, lats, capacity, ray_ids, t0, t1, vec4);
     }
 }
 

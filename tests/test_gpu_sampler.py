@@ -263,6 +263,22 @@ def test_many_runs_per_ray(variant):
     for vox in (False, True):
         got = gpu_sample(g, o, d, 0.0, 8.0, step, variant[1], voxel_ids=vox)
         assert_same(got, ref, f"checkerboard {variant} vox={vox}")
+    # the one-call pass (scan inside the expansion; the lost rays' first
+    # outputs then come from the count pass's sums), exact and short capacity
+    S = int(ref["offsets"][-1])
+    sp = api.Sampler(g, len(o), 0.0, 8.0, step, variant[1])
+    od, dd = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
+    for cap in (S, S // 2):
+        ids = torch.full((cap,), -7, dtype=torch.int32, device="cuda")
+        t0 = torch.zeros(cap, device="cuda")
+        t1 = torch.zeros(cap, device="cuda")
+        offsets, overflow = sp.rays(od, dd, ids, t0, t1)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(offsets.cpu().numpy(), ref["offsets"], err_msg=f"one call {variant} cap={cap}")
+        assert int(overflow.item()) == (1 if cap < S else 0)
+        np.testing.assert_array_equal(ids.cpu().numpy(), ref["ray_ids"][:cap], err_msg=f"one call {variant} cap={cap}")
+        np.testing.assert_array_equal(t0.cpu().numpy(), ref["t0"][:cap], err_msg=f"one call {variant} cap={cap}")
+        np.testing.assert_array_equal(t1.cpu().numpy(), ref["t1"][:cap], err_msg=f"one call {variant} cap={cap}")
 
 
 # ------------------------------------------------------------------ structure, edges, errors
