@@ -506,6 +506,32 @@ static int32_t sample_voxel_id(const ray_ctx *x, const analyzer *z, const int *c
     return voxel_id(x->R, z->lev, c);
 }
 
+/* The samples a cell holds: the lattice points in its parameter interval
+ * (t0, t1] (a voxel owns (entry, exit], the reading of Alg. 1's tests), none
+ * beyond tmax.  The lattice only moves forward, as the cells of a ray come
+ * in increasing t. */
+static void emit_cell(lattice *q, float t0, float t1, float tmax, const ray_ctx *x, const analyzer *z,
+                      const int *cell, sink *out)
+{
+    while (q->t <= t0) lat_advance(q);
+    for (; q->t <= t1 && q->t <= tmax; lat_advance(q)) emit(out, q->t, q->tnext, sample_voxel_id(x, z, cell, q->t));
+}
+
+/* The next cell the loop looks at: with skip = 0 the next cell along the ray
+ * whatever it holds (Alg. 1 visits every cell and tests it); with skip = 1
+ * the next occupied one, passing all empty cells before it (Alg. 2).  0 when
+ * the segment has no such cell left. */
+static int next_cell(analyzer *z, int skip, int *cell, float *t0, float *t1, int *occ)
+{
+    do {
+        if (!analyzer_next(z, cell, t0, t1, occ)) return 0;
+    } while (skip && !*occ);
+    return 1;
+}
+
+/* All samples of a ray: each segment's cells in ray order, every occupied
+ * cell giving the lattice points it holds.  Both loop structures find the
+ * same occupied cells, so they give the same samples. */
 static void march(const ray_ctx *x, const orc_vdb *vdb, int skip, const orc_step *s, float tmin, float tmax,
                   sink *out)
 {
@@ -517,31 +543,11 @@ static void march(const ray_ctx *x, const orc_vdb *vdb, int skip, const orc_step
         if (seg[si].b < q.t) continue;  /* holds no lattice point still ahead */
         analyzer z;
         analyzer_start(&z, x, vdb, &seg[si], tmin);
-        while (q.t <= tmax) {
-            int cell[3], occ;
-            float t0, t1;
-            if (!analyzer_next(&z, cell, &t0, &t1, &occ)) break;
-            if (skip) {
-                /* Alg. 2: pass over every empty cell, then march the occupied one. */
-                int found = occ;
-                while (!found) {
-                    if (!analyzer_next(&z, cell, &t0, &t1, &occ)) break;
-                    found = occ;
-                }
-                if (!found) break;
-                while (q.t <= t0) lat_advance(&q);
-                while (q.t <= t1 && q.t <= tmax) {
-                    emit(out, q.t, q.tnext, sample_voxel_id(x, &z, cell, q.t));
-                    lat_advance(&q);
-                }
-            } else {
-                /* Alg. 1: visit the cell, emit the lattice points in it if occupied. */
-                while (q.t <= t0) lat_advance(&q);
-                while (q.t <= t1 && q.t <= tmax) {
-                    if (occ) emit(out, q.t, q.tnext, sample_voxel_id(x, &z, cell, q.t));
-                    lat_advance(&q);
-                }
-            }
+        int cell[3], occ;
+        float t0, t1;
+        while (q.t <= tmax && next_cell(&z, skip, cell, &t0, &t1, &occ)) {
+            if (t0 >= tmax) break;  /* a cell starting at or past tmax holds no sample */
+            if (occ) emit_cell(&q, t0, t1, tmax, x, &z, cell, out);
         }
     }
 }
