@@ -57,10 +57,11 @@ __device__ __forceinline__ int scene_of_item(const SceneDesc *scenes, int n, int
     return s;
 }
 
+// The descriptors are in queue order, not in ray order: search them all.
 __device__ __forceinline__ int scene_of_ray(const SceneDesc *scenes, int n, int64_t gr) {
-    int s = 0;
-    while (s + 1 < n && scenes[s + 1].first <= gr) ++s;
-    return s;
+    for (int s = 0; s < n; ++s)
+        if (gr >= scenes[s].first && gr < scenes[s].first + scenes[s].n) return s;
+    return 0;
 }
 
 // Persistent: every workgroup loops pulling items until the queue runs dry,
@@ -402,6 +403,15 @@ extern "C" ogv_status ogv_batch_create(const ogv_scene *scenes, int32_t n, int32
         first[i] = d.first;
     }
     first[n] = total;
+    // The queue hands out the scenes' chunks in order of decreasing per-ray
+    // cost (resolution times levels: the cells a ray can cross), so the
+    // scenes whose waves run longest start first instead of forming the
+    // launch's tail; the output stays in scene order (each descriptor keeps
+    // its first global ray).
+    std::stable_sort(b->desc.begin(), b->desc.end(), [](const SceneDesc &x, const SceneDesc &y) {
+        const int64_t cx = (int64_t)x.g.R * x.g.L, cy = (int64_t)y.g.R * y.g.L;
+        return cx != cy ? cx > cy : x.n > y.n;
+    });
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(b->lats_dev, lats.data(), sizeof(Lattice) * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
