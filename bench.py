@@ -361,7 +361,8 @@ def cpu_baseline(obj_stride=1, unb_stride=2):
     the object workload (every `obj_stride`-th ray) and the four-cascade
     workload (every `unb_stride`-th ray), each the median of 3 runs; O3 and O2
     on one thread over every 64th object ray; brute force (O1) on all of the
-    64x64 small workload.  `value` is O3 on the object workload."""
+    64x64 small workload.  `value` is O3 on the object workload.  Also the
+    cells per ray that the dense, hierarchical and sub-leaf walks visit."""
     import numpy as np
     import oracle
     from paper_2404_10272_amd import scenes
@@ -393,6 +394,16 @@ def cpu_baseline(obj_stride=1, unb_stride=2):
     leg("unbounded_hdda", unb, unb_stride, "hdda_branch", threads)
     leg("unbounded_dense_dda", unb, unb_stride, "dense_branch", threads)
     leg("small_brute_force", scenes.workload("small"), 1, "brute", threads)
+    # cells a ray's walk visits, per traversal (every 16th ray): what the walk
+    # kernels' time scales with
+    cells = {}
+    for w in (obj, unb):
+        scene = oracle.Scene(w.occ, w.boxes)
+        o = np.ascontiguousarray(w.origins[::16])
+        d = np.ascontiguousarray(w.dirs[::16])
+        for m in ("dense_branch", "hdda_branch", "subleaf_branch"):
+            c = oracle.cell_counts(scene, o, d, w.near, w.far, w.step, m, ilog2=w.ilog2, threads=threads)
+            cells[f"{w.name}_{m}"] = {"mean": float(c.mean()), "max": int(c.max()), "rays": int(c.shape[0])}
     model = ""
     try:
         model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
@@ -403,7 +414,8 @@ def cpu_baseline(obj_stride=1, unb_stride=2):
             "sample": f"object workload, every {obj_stride}th ray ({head['rays']} rays, {head['samples']} samples), "
                       f"VDB + hierarchical DDA (Alg. 1 loop), count + fill, median of 3 runs on {threads} threads; "
                       f"{spent:.1f} s of oracle time over all legs",
-            "methods": methods, "host": {"cpus": os.cpu_count(), "threads_allowed": threads, "model": model}}
+            "methods": methods, "cells_per_ray": cells,
+            "host": {"cpus": os.cpu_count(), "threads_allowed": threads, "model": model}}
 
 
 def main():

@@ -5,10 +5,12 @@ the benchmark may import this package; the product path (the HIP library and
 its Python binding) never does, and this package never imports the product.
 
 * ``og_oracle.c`` (loaded here through ctypes) enumerates the fixed-step
-  samples of every ray in three independent ways: brute force over the
-  lattice, a dense voxel DDA and a VDB tree with hierarchical DDA, each
-  driven as in Alg. 1 ("DDA branch") or Alg. 2 ("DDA skip") of the paper's
-  supplementary material.  Its header states the binary32 definition.
+  samples of every ray in independent ways: brute force over the lattice, a
+  dense voxel DDA, and a VDB tree with hierarchical DDA (whose leaf voxels
+  may also merge into uniform 4^3 / 2^3 sub-blocks), each DDA driven as in
+  Alg. 1 ("DDA branch") or Alg. 2 ("DDA skip") of the paper's supplementary
+  material, and counts the cells each walk visits.  Its header states the
+  binary32 definition.
 * ``composite.py`` is the FP64 volume-rendering composite and its gradient.
 """
 import ctypes
@@ -23,9 +25,10 @@ from .distance import chessboard_distance, chessboard_distance_brute  # noqa: F4
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libogoracle.so")
 
-BRUTE, DENSE_BRANCH, DENSE_SKIP, HDDA_BRANCH, HDDA_SKIP = 0, 1, 2, 3, 4
+BRUTE, DENSE_BRANCH, DENSE_SKIP, HDDA_BRANCH, HDDA_SKIP, SUBLEAF_BRANCH, SUBLEAF_SKIP = 0, 1, 2, 3, 4, 5, 6
 METHODS = {"brute": BRUTE, "dense_branch": DENSE_BRANCH, "dense_skip": DENSE_SKIP,
-           "hdda_branch": HDDA_BRANCH, "hdda_skip": HDDA_SKIP}
+           "hdda_branch": HDDA_BRANCH, "hdda_skip": HDDA_SKIP,
+           "subleaf_branch": SUBLEAF_BRANCH, "subleaf_skip": SUBLEAF_SKIP}
 
 
 class _Grid(ctypes.Structure):
@@ -57,6 +60,8 @@ def _load():
     lib.orc_count.argtypes = [P(_Grid), ctypes.c_void_p, P(_Step), f32p, f32p, ctypes.c_int64, ctypes.c_float,
                               ctypes.c_float, ctypes.c_int32, i64p, ctypes.c_int32]
     lib.orc_count.restype = ctypes.c_int32
+    lib.orc_cells.argtypes = lib.orc_count.argtypes
+    lib.orc_cells.restype = ctypes.c_int32
     lib.orc_fill.argtypes = [P(_Grid), ctypes.c_void_p, P(_Step), f32p, f32p, ctypes.c_int64, ctypes.c_float,
                              ctypes.c_float, ctypes.c_int32, i64p, i32p, f32p, f32p, i32p, ctypes.c_int32]
     lib.orc_fill.restype = ctypes.c_int64
@@ -130,7 +135,7 @@ def _step_struct(step):
 
 def _method_args(scene, method, ilog2):
     m = METHODS[method] if isinstance(method, str) else int(method)
-    vdb = scene.vdb(ilog2) if m in (HDDA_BRANCH, HDDA_SKIP) else None
+    vdb = scene.vdb(ilog2) if m in (HDDA_BRANCH, HDDA_SKIP, SUBLEAF_BRANCH, SUBLEAF_SKIP) else None
     return m, vdb
 
 
@@ -164,6 +169,21 @@ def sample_counts(scene, origins, dirs, tmin, tmax, step, method="hdda_skip", il
     if rc != 0:
         raise ValueError("oracle rejected the method")
     return counts
+
+
+def cell_counts(scene, origins, dirs, tmin, tmax, step, method="hdda_branch", ilog2=3, threads=0):
+    """Cells each ray's walk visits (int64[N]) for a DDA method (not brute force)."""
+    lib = _load()
+    m, vdb = _method_args(scene, method, ilog2)
+    o = np.ascontiguousarray(origins, np.float32).reshape(-1, 3)
+    d = np.ascontiguousarray(dirs, np.float32).reshape(-1, 3)
+    cells = np.zeros(o.shape[0], np.int64)
+    st = _step_struct(step)
+    rc = lib.orc_cells(ctypes.byref(scene._g), vdb, ctypes.byref(st), _fptr(o), _fptr(d), o.shape[0],
+                       tmin, tmax, m, _lptr(cells), int(threads))
+    if rc != 0:
+        raise ValueError("oracle rejected the method")
+    return cells
 
 
 def sample_rays(scene, origins, dirs, tmin, tmax, step, method="hdda_skip", ilog2=3, threads=0):

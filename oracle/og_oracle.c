@@ -46,7 +46,13 @@
  *   method 3/4  a VDB tree (root table -> internal node -> 8^3 leaf, with
  *             uniform blocks pruned into tiles, Sec. 3) and a level-adaptive
  *             DDA that steps over a whole tile at once (HDDA, Sec. 2.3),
+ *             driven as in Alg. 1 or Alg. 2;
+ *   method 5/6  the same tree and DDA, where inside a leaf the cell is the
+ *             largest uniform (all empty or all occupied) aligned 4^3 or 2^3
+ *             sub-block holding the voxel, else the voxel: empty space is
+ *             passed by powers of two down to single voxels (Fig. 1),
  *             driven as in Alg. 1 or Alg. 2.
+ * Every way also reports how many cells a ray's walk visits (orc_cells).
  *
  * Readings of the algorithms (where the printed text is ambiguous):
  *   - Alg. 2's inner "repeat ... until" loop is read as "repeat until the
@@ -365,6 +371,7 @@ static int ray_segments(const ray_ctx *x, segment *seg)
 typedef struct {
     const ray_ctx *x;
     const orc_vdb *vdb;   /* NULL: dense voxel DDA; else level-adaptive HDDA */
+    int sub;              /* HDDA only: leaf voxels may merge into uniform 4^3 / 2^3 sub-blocks */
     int lev;
     int c[3];
     float seg_a, seg_b;
@@ -390,10 +397,12 @@ static void axis_bounds(const ray_ctx *x, int lev, int a, int lo_m, int hi_m, fl
     }
 }
 
-static void analyzer_start(analyzer *z, const ray_ctx *x, const orc_vdb *vdb, const segment *s, float tmin)
+static void analyzer_start(analyzer *z, const ray_ctx *x, const orc_vdb *vdb, int sub, const segment *s,
+                           float tmin)
 {
     z->x = x;
     z->vdb = vdb;
+    z->sub = sub;
     z->lev = s->lev;
     z->seg_a = s->a;
     z->seg_b = s->b;
@@ -407,8 +416,23 @@ static void analyzer_start(analyzer *z, const ray_ctx *x, const orc_vdb *vdb, co
     if (!inside(x->R, z->c)) z->live = 0;
 }
 
-/* The VDB cell holding voxel c: its edge length in voxels and occupancy. */
-static void vdb_lookup(const orc_vdb *v, int lev, const int *c, int *D, int *occ_out)
+/* 1 if the aligned cube of e^3 voxels at (b0, b1, b2) inside leaf `leaf`
+ * holds one value throughout. */
+static int leaf_cube_uniform(const orc_vdb *v, int32_t leaf, int b0, int b1, int b2, int e)
+{
+    const uint8_t *L = v->leaf_vox + (size_t)leaf * 512;
+    uint8_t first = L[(b0 * 8 + b1) * 8 + b2];
+    for (int i = b0; i < b0 + e; ++i)
+        for (int j = b1; j < b1 + e; ++j)
+            for (int k = b2; k < b2 + e; ++k)
+                if (L[(i * 8 + j) * 8 + k] != first) return 0;
+    return 1;
+}
+
+/* The VDB cell holding voxel c: its edge length in voxels and occupancy.
+ * With sub, a leaf voxel's cell is the largest uniform aligned 4^3 or 2^3
+ * sub-block of its leaf holding it, else the voxel itself. */
+static void vdb_lookup(const orc_vdb *v, int lev, const int *c, int sub, int *D, int *occ_out)
 {
     int rc[3], sl[3], lc[3];
     for (int a = 0; a < 3; ++a) {
@@ -428,8 +452,16 @@ static void vdb_lookup(const orc_vdb *v, int lev, const int *c, int *D, int *occ
         *occ_out = v->slot_kind[si];
         return;
     }
+    const int32_t leaf = v->slot_leaf[si];
     *D = 1;
-    *occ_out = v->leaf_vox[(size_t)v->slot_leaf[si] * 512 + (lc[0] * 8 + lc[1]) * 8 + lc[2]] != 0;
+    *occ_out = v->leaf_vox[(size_t)leaf * 512 + (lc[0] * 8 + lc[1]) * 8 + lc[2]] != 0;
+    if (sub) {
+        for (int e = 4; e >= 2; e /= 2)
+            if (leaf_cube_uniform(v, leaf, lc[0] / e * e, lc[1] / e * e, lc[2] / e * e, e)) {
+                *D = e;
+                break;
+            }
+    }
 }
 
 /* Next cell: returns 0 when the segment is exhausted. */
@@ -466,7 +498,7 @@ static int analyzer_next(analyzer *z, int *cell, float *t0, float *t1, int *occ_
     /* Level-adaptive DDA: the cell is the largest uniform VDB cell (root
      * tile, internal tile or voxel) that holds the current voxel. */
     int D, occ;
-    vdb_lookup(z->vdb, z->lev, z->c, &D, &occ);
+    vdb_lookup(z->vdb, z->lev, z->c, z->sub, &D, &occ);
     float exit_t = INFINITY;
     for (int a = 0; a < 3; ++a) {
         if (x->zero[a]) continue;
@@ -520,11 +552,13 @@ static void emit_cell(lattice *q, float t0, float t1, float tmax, const ray_ctx 
 /* The next cell the loop looks at: with skip = 0 the next cell along the ray
  * whatever it holds (Alg. 1 visits every cell and tests it); with skip = 1
  * the next occupied one, passing all empty cells before it (Alg. 2).  0 when
- * the segment has no such cell left. */
-static int next_cell(analyzer *z, int skip, int *cell, float *t0, float *t1, int *occ)
+ * the segment has no such cell left.  *visited counts every cell the
+ * analyzer returns, occupied or not. */
+static int next_cell(analyzer *z, int skip, int *cell, float *t0, float *t1, int *occ, int64_t *visited)
 {
     do {
         if (!analyzer_next(z, cell, t0, t1, occ)) return 0;
+        *visited += 1;
     } while (skip && !*occ);
     return 1;
 }
@@ -532,8 +566,8 @@ static int next_cell(analyzer *z, int skip, int *cell, float *t0, float *t1, int
 /* All samples of a ray: each segment's cells in ray order, every occupied
  * cell giving the lattice points it holds.  Both loop structures find the
  * same occupied cells, so they give the same samples. */
-static void march(const ray_ctx *x, const orc_vdb *vdb, int skip, const orc_step *s, float tmin, float tmax,
-                  sink *out)
+static void march(const ray_ctx *x, const orc_vdb *vdb, int sub, int skip, const orc_step *s, float tmin,
+                  float tmax, sink *out, int64_t *visited)
 {
     segment seg[2 * ORC_MAX_LEVELS];
     int ns = ray_segments(x, seg);
@@ -542,10 +576,10 @@ static void march(const ray_ctx *x, const orc_vdb *vdb, int skip, const orc_step
     for (int si = 0; si < ns && q.t <= tmax; ++si) {
         if (seg[si].b < q.t) continue;  /* holds no lattice point still ahead */
         analyzer z;
-        analyzer_start(&z, x, vdb, &seg[si], tmin);
+        analyzer_start(&z, x, vdb, sub, &seg[si], tmin);
         int cell[3], occ;
         float t0, t1;
-        while (q.t <= tmax && next_cell(&z, skip, cell, &t0, &t1, &occ)) {
+        while (q.t <= tmax && next_cell(&z, skip, cell, &t0, &t1, &occ, visited)) {
             if (t0 >= tmax) break;  /* a cell starting at or past tmax holds no sample */
             if (occ) emit_cell(&q, t0, t1, tmax, x, &z, cell, out);
         }
@@ -555,8 +589,9 @@ static void march(const ray_ctx *x, const orc_vdb *vdb, int skip, const orc_step
 /* ------------------------------------------------------------------ */
 /* Public entry points (ctypes). */
 
-int64_t orc_ray(const orc_grid *g, const orc_vdb *vdb, const orc_step *s, const float *o, const float *d,
-                float tmin, float tmax, int32_t method, float *t0, float *t1, int32_t *vox, int64_t cap)
+static int64_t ray_run(const orc_grid *g, const orc_vdb *vdb, const orc_step *s, const float *o, const float *d,
+                       float tmin, float tmax, int32_t method, float *t0, float *t1, int32_t *vox, int64_t cap,
+                       int64_t *visited)
 {
     sink out = {0, cap, t0, t1, vox};
     if (!(tmin <= tmax)) return 0;
@@ -564,27 +599,60 @@ int64_t orc_ray(const orc_grid *g, const orc_vdb *vdb, const orc_step *s, const 
     if (!ray_init(&x, g, o, d)) return 0;
     switch (method) {
     case 0: brute_force(&x, s, tmin, tmax, &out); break;
-    case 1: march(&x, NULL, 0, s, tmin, tmax, &out); break;
-    case 2: march(&x, NULL, 1, s, tmin, tmax, &out); break;
-    case 3: march(&x, vdb, 0, s, tmin, tmax, &out); break;
-    case 4: march(&x, vdb, 1, s, tmin, tmax, &out); break;
+    case 1: march(&x, NULL, 0, 0, s, tmin, tmax, &out, visited); break;
+    case 2: march(&x, NULL, 0, 1, s, tmin, tmax, &out, visited); break;
+    case 3: march(&x, vdb, 0, 0, s, tmin, tmax, &out, visited); break;
+    case 4: march(&x, vdb, 0, 1, s, tmin, tmax, &out, visited); break;
+    case 5: march(&x, vdb, 1, 0, s, tmin, tmax, &out, visited); break;
+    case 6: march(&x, vdb, 1, 1, s, tmin, tmax, &out, visited); break;
     default: out.count = -1;
     }
     ray_free(&x);
     return out.count;
 }
 
+int64_t orc_ray(const orc_grid *g, const orc_vdb *vdb, const orc_step *s, const float *o, const float *d,
+                float tmin, float tmax, int32_t method, float *t0, float *t1, int32_t *vox, int64_t cap)
+{
+    int64_t visited = 0;
+    return ray_run(g, vdb, s, o, d, tmin, tmax, method, t0, t1, vox, cap, &visited);
+}
+
+static int bad_method(const orc_vdb *vdb, int32_t method)
+{
+    return method < 0 || method > 6 || (method >= 3 && vdb == NULL);
+}
+
 /* counts[i] = number of samples of ray i.  Returns 0, or -1 on a bad method. */
 int32_t orc_count(const orc_grid *g, const orc_vdb *vdb, const orc_step *s, const float *o, const float *d,
                   int64_t n, float tmin, float tmax, int32_t method, int64_t *counts, int32_t nthreads)
 {
-    if (method < 0 || method > 4 || ((method == 3 || method == 4) && vdb == NULL)) return -1;
+    if (bad_method(vdb, method)) return -1;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 256)
 #endif
     for (int64_t i = 0; i < n; ++i)
         counts[i] = orc_ray(g, vdb, s, o + 3 * i, d + 3 * i, tmin, tmax, method, NULL, NULL, NULL, 0);
+    return 0;
+}
+
+/* cells[i] = number of cells ray i's walk visits (occupied or not) before it
+ * ends, for the DDA methods 1..6 (brute force visits no cells).  Returns 0,
+ * or -1 on a bad method. */
+int32_t orc_cells(const orc_grid *g, const orc_vdb *vdb, const orc_step *s, const float *o, const float *d,
+                  int64_t n, float tmin, float tmax, int32_t method, int64_t *cells, int32_t nthreads)
+{
+    if (bad_method(vdb, method) || method == 0) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 256)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t visited = 0;
+        ray_run(g, vdb, s, o + 3 * i, d + 3 * i, tmin, tmax, method, NULL, NULL, NULL, 0, &visited);
+        cells[i] = visited;
+    }
     return 0;
 }
 

@@ -1,4 +1,4 @@
-"""The oracle's five ways of sampling reproduce hand-derived answers exactly.
+"""The oracle's seven ways of sampling reproduce hand-derived answers exactly.
 
 The answers in tests/golden/handmade_cases.json were derived by hand from the
 ownership rule (a voxel owns (entry, exit], the "<=" tests of Alg. 1), the
@@ -12,7 +12,7 @@ import oracle
 from tests import handmade
 
 DATA = handmade.load()
-METHODS = ["brute", "dense_branch", "dense_skip", "hdda_branch", "hdda_skip"]
+METHODS = ["brute", "dense_branch", "dense_skip", "hdda_branch", "hdda_skip", "subleaf_branch", "subleaf_skip"]
 
 
 @pytest.mark.parametrize("case", DATA["cases"], ids=lambda c: c["name"])

@@ -1,8 +1,9 @@
 """Properties the sampling rule fixes, checked on the oracle with random tiny inputs.
 
-* Brute force, dense DDA (Alg. 1 branch / Alg. 2 skip) and VDB + hierarchical
-  DDA (branch / skip) give the identical sample list: they differ only in how
-  empty space is skipped (Sec. 2.3, Sec. 3).
+* Brute force, dense DDA (Alg. 1 branch / Alg. 2 skip), VDB + hierarchical
+  DDA (branch / skip) and the same with uniform sub-blocks inside leaves give
+  the identical sample list: they differ only in how empty space is skipped
+  (Sec. 2.3, Fig. 1, Sec. 3).
 * Occupancy enters point by point: S(G1 | G2) = S(G1) | S(G2),
   S(G1 & G2) = S(G1) & S(G2), S(~G) = S(full) - S(G).
 * Exact symmetries: permuting the axes of grid and ray permutes voxel ids and
@@ -19,7 +20,7 @@ from hypothesis import given, settings, strategies as st, HealthCheck
 
 import oracle
 
-METHODS = ["brute", "dense_branch", "dense_skip", "hdda_branch", "hdda_skip"]
+METHODS = ["brute", "dense_branch", "dense_skip", "hdda_branch", "hdda_skip", "subleaf_branch", "subleaf_skip"]
 
 
 def random_scene(rng, R, L, p):
