@@ -1,7 +1,8 @@
 """The Python example of the README runs as written: one ray through a solid
 50^3 block of a 128^3 grid gives exactly the lattice points inside the block
 (worked out in binary32 from the block's dyadic planes), the composite
-differentiates, and a refresh with the same occupancy changes nothing."""
+differentiates, and a refresh with the same occupancy (given directly, or as a
+density cache) changes nothing."""
 import numpy as np
 import pytest
 import torch
@@ -41,3 +42,9 @@ def test_readme_example():
     grid.refresh(occ)
     out2 = api.sample_rays(grid, o, d, near=2.0, far=6.0, step=api.make_step("const", dt=5e-3))
     assert torch.equal(out2["t0"], out["t0"])
+    # the density-cache refresh with the occupancy as density leaves the same grid
+    cache = torch.zeros(occ.shape, device="cuda")
+    grid.refresh_density(cache, density=occ.float(), decay=0.95, threshold=0.01)
+    assert torch.equal(cache, occ.float())
+    out3 = api.sample_rays(grid, o, d, near=2.0, far=6.0, step=api.make_step("const", dt=5e-3))
+    assert torch.equal(out3["t0"], out["t0"])

@@ -281,6 +281,38 @@ def test_many_runs_per_ray(variant):
         np.testing.assert_array_equal(t1.cpu().numpy(), ref["t1"][:cap], err_msg=f"one call {variant} cap={cap}")
 
 
+def test_one_call_scan_path_boundary():
+    """The one-call pass scans inside the expansion up to 192 scan tiles
+    (786,432 rays) and launches the scan beyond: ray counts just below, at
+    and just above that size, and a ragged last tile, all against the
+    oracle, with the VDB and dense grids."""
+    R = 32
+    rng = np.random.default_rng(5)
+    occ = (rng.random((1, R, R, R)) < 0.25).astype(np.uint8)
+    boxes = np.asarray([[-1, -1, -1, 1, 1, 1]], np.float32)
+    n_max = 192 * 4096 + 1
+    o, d = scenes.random_rays(n_max, rng, -1.5, 1.5)
+    step = oracle.make_step("const", dt=0.02)
+    ref_all = oracle.sample_rays(oracle.Scene(occ, boxes), o, d, 0.0, 4.0, step, "dense_branch", threads=16)
+    od, dd = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
+    for kind in ("vdb", "dense"):
+        g = gpu_grid(kind, occ, boxes, 1)
+        for n in (192 * 4096 - 1000, 192 * 4096, 192 * 4096 + 1):
+            S = int(ref_all["offsets"][n])
+            sp = api.Sampler(g, n, 0.0, 4.0, step, "branch")
+            ids = torch.full((S,), -7, dtype=torch.int32, device="cuda")
+            t0 = torch.zeros(S, device="cuda")
+            t1 = torch.zeros(S, device="cuda")
+            offsets, overflow = sp.rays(od[:n], dd[:n], ids, t0, t1)
+            torch.cuda.synchronize()
+            what = f"{kind} n={n}"
+            np.testing.assert_array_equal(offsets.cpu().numpy(), ref_all["offsets"][:n + 1], err_msg=what)
+            assert int(overflow.item()) == 0, what
+            np.testing.assert_array_equal(ids.cpu().numpy(), ref_all["ray_ids"][:S], err_msg=what)
+            np.testing.assert_array_equal(t0.cpu().numpy(), ref_all["t0"][:S], err_msg=what)
+            np.testing.assert_array_equal(t1.cpu().numpy(), ref_all["t1"][:S], err_msg=what)
+
+
 # ------------------------------------------------------------------ structure, edges, errors
 
 @pytest.mark.parametrize("name", ["small", "object", "unbounded"])
