@@ -7,7 +7,7 @@ its Python binding) never does, and this package never imports the product.
 * ``og_oracle.c`` (loaded here through ctypes) enumerates the fixed-step
   samples of every ray in independent ways: brute force over the lattice, a
   dense voxel DDA, and a VDB tree with hierarchical DDA (whose leaf voxels
-  may also merge into uniform 4^3 / 2^3 sub-blocks), each DDA driven as in
+  may also merge into uniform 4^3 sub-blocks), each DDA driven as in
   Alg. 1 ("DDA branch") or Alg. 2 ("DDA skip") of the paper's supplementary
   material, and counts the cells each walk visits.  Its header states the
   binary32 definition.

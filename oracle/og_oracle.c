@@ -48,10 +48,10 @@
  *             DDA that steps over a whole tile at once (HDDA, Sec. 2.3),
  *             driven as in Alg. 1 or Alg. 2;
  *   method 5/6  the same tree and DDA, where inside a leaf the cell is the
- *             largest uniform (all empty or all occupied) aligned 4^3 or 2^3
- *             sub-block holding the voxel, else the voxel: empty space is
- *             passed by powers of two down to single voxels (Fig. 1),
- *             driven as in Alg. 1 or Alg. 2.
+ *             aligned 4^3 sub-block holding the voxel when it is uniform (all
+ *             empty or all occupied), else the voxel: empty space is passed by
+ *             powers of two down to single voxels (Fig. 1), driven as in
+ *             Alg. 1 or Alg. 2.
  * Every way also reports how many cells a ray's walk visits (orc_cells).
  *
  * Readings of the algorithms (where the printed text is ambiguous):
@@ -371,7 +371,7 @@ static int ray_segments(const ray_ctx *x, segment *seg)
 typedef struct {
     const ray_ctx *x;
     const orc_vdb *vdb;   /* NULL: dense voxel DDA; else level-adaptive HDDA */
-    int sub;              /* HDDA only: leaf voxels may merge into uniform 4^3 / 2^3 sub-blocks */
+    int sub;              /* HDDA only: leaf voxels merge into uniform 4^3 sub-blocks */
     int lev;
     int c[3];
     float seg_a, seg_b;
@@ -430,8 +430,8 @@ static int leaf_cube_uniform(const orc_vdb *v, int32_t leaf, int b0, int b1, int
 }
 
 /* The VDB cell holding voxel c: its edge length in voxels and occupancy.
- * With sub, a leaf voxel's cell is the largest uniform aligned 4^3 or 2^3
- * sub-block of its leaf holding it, else the voxel itself. */
+ * With sub, a leaf voxel's cell is the aligned 4^3 sub-block of its leaf
+ * holding it when that is uniform, else the voxel itself. */
 static void vdb_lookup(const orc_vdb *v, int lev, const int *c, int sub, int *D, int *occ_out)
 {
     int rc[3], sl[3], lc[3];
@@ -455,13 +455,7 @@ static void vdb_lookup(const orc_vdb *v, int lev, const int *c, int sub, int *D,
     const int32_t leaf = v->slot_leaf[si];
     *D = 1;
     *occ_out = v->leaf_vox[(size_t)leaf * 512 + (lc[0] * 8 + lc[1]) * 8 + lc[2]] != 0;
-    if (sub) {
-        for (int e = 4; e >= 2; e /= 2)
-            if (leaf_cube_uniform(v, leaf, lc[0] / e * e, lc[1] / e * e, lc[2] / e * e, e)) {
-                *D = e;
-                break;
-            }
-    }
+    if (sub && leaf_cube_uniform(v, leaf, lc[0] / 4 * 4, lc[1] / 4 * 4, lc[2] / 4 * 4, 4)) *D = 4;
 }
 
 /* Next cell: returns 0 when the segment is exhausted. */

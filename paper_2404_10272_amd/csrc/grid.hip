@@ -425,21 +425,11 @@ __global__ void __launch_bounds__(256) node_write_kernel(BuildDims b, const int3
     }
 }
 
-// Uniform sub-blocks of a leaf given its eight words (word x, bit y*8 + z):
-// u2 bit ((x>>1)*4 + (y>>1))*4 + (z>>1) is set when the eight voxels of that
-// 2^3 sub-block are all occupied or all empty, u4 bit ((x>>2)*2 + (y>>2))*2 +
-// (z>>2) likewise for the 64 voxels of a 4^3 sub-block.
-__device__ void leaf_uniform_subblocks(const uint64_t *w, uint64_t &u2, uint64_t &u4) {
-    u2 = 0;
-    u4 = 0;
-    for (int xp = 0; xp < 4; ++xp) {
-        const uint64_t a = w[2 * xp] & w[2 * xp + 1], o = w[2 * xp] | w[2 * xp + 1];
-        for (int yp = 0; yp < 4; ++yp)
-            for (int zp = 0; zp < 4; ++zp) {
-                const uint64_t m = 0x303ull << (16 * yp + 2 * zp);   // y in {2yp, 2yp+1}, z in {2zp, 2zp+1}
-                if ((a & m) == m || (o & m) == 0) u2 |= 1ull << ((xp * 4 + yp) * 4 + zp);
-            }
-    }
+// Uniform 4^3 sub-blocks of a leaf given its eight words (word x, bit
+// y*8 + z): bit ((x>>2)*2 + (y>>2))*2 + (z>>2) is set when the 64 voxels of
+// that sub-block are all occupied or all empty.
+__device__ uint64_t leaf_uniform_quarters(const uint64_t *w) {
+    uint64_t u4 = 0;
     for (int xq = 0; xq < 2; ++xq) {
         uint64_t a = ~0ull, o = 0;
         for (int x = 4 * xq; x < 4 * xq + 4; ++x) {
@@ -452,6 +442,7 @@ __device__ void leaf_uniform_subblocks(const uint64_t *w, uint64_t &u2, uint64_t
                 if ((a & m) == m || (o & m) == 0) u4 |= 1ull << ((xq * 2 + yq) * 2 + zq);
             }
     }
+    return u4;
 }
 
 // gate (nullable): when *gate is 0 only the leaves of dirty blocks (dirty[e]
@@ -469,12 +460,7 @@ __global__ void leaf_write_kernel(BuildDims b, const int32_t *__restrict__ mixed
     if (all && e == 0 && j == 0) counts->n_leaves = leaf_idx[b.n_block];
     if (!mixed[e]) return;
     leaves[leaf_idx[e] * 8 + j] = masks[e * 8 + j];
-    if (j == 0) {
-        uint64_t u2, u4;
-        leaf_uniform_subblocks(masks + e * 8, u2, u4);
-        sub[leaf_idx[e] * 2] = u2;
-        sub[leaf_idx[e] * 2 + 1] = u4;
-    }
+    if (j == 0) sub[leaf_idx[e]] = leaf_uniform_quarters(masks + e * 8);
 }
 
 // decode a VDB tree into dense bytes, one thread per voxel
@@ -766,7 +752,7 @@ extern "C" ogv_status ogv_vdb_build(int32_t L, int32_t R, const float *boxes, co
     size_t o_rank = take(sizeof(uint32_t) * b.n_root * b.W);
     size_t o_slot = take(sizeof(int32_t) * b.n_root * b.n_slot);
     size_t o_leaves = take(sizeof(uint64_t) * 8 * b.n_block);
-    size_t o_sub = take(sizeof(uint64_t) * 2 * b.n_block);
+    size_t o_sub = take(sizeof(uint64_t) * b.n_block);
     size_t total = off;
     // build scratch
     off = 0;
@@ -872,7 +858,7 @@ extern "C" ogv_status ogv_grid_info_get(const ogv_grid *grid, ogv_grid_info *inf
         g->counts_ready = true;
         const int64_t n_root = (int64_t)v.L * v.NR * v.NR * v.NR;
         g->used_bytes = (size_t)(n_root * 4 + g->counts_host.n_nodes * (int64_t)v.W * (8 + 8 + 4) +
-                                 g->counts_host.n_nodes * (int64_t)v.S * v.S * v.S * 4 + g->counts_host.n_leaves * (64 + 16));
+                                 g->counts_host.n_nodes * (int64_t)v.S * v.S * v.S * 4 + g->counts_host.n_leaves * (64 + 8));
     }
     const VdbCounts &c = g->counts_host;
     info->bytes = (int64_t)g->used_bytes;

@@ -44,11 +44,10 @@ constexpr int kMaxLevels = OGV_MAX_LEVELS;
 //                              -2 full tile (the node's child table, which
 //                              the walk reads; the masks serve decoding)
 //   leaves uint64 [leaves][8] word x (voxel x&7), bit (y&7)*8 + (z&7)
-//   sub    uint64 [leaves][2] uniform sub-blocks of each leaf: word 0 bit
-//                              ((x>>1)*4 + (y>>1))*4 + (z>>1) for the 2^3
-//                              sub-blocks, word 1 bit ((x>>2)*2 + (y>>2))*2
-//                              + (z>>2) for the 4^3 ones (x, y, z in 0..7);
-//                              a set bit: all its voxels share one value
+//   sub    uint64 [leaves]    uniform 4^3 sub-blocks of each leaf: bit
+//                              ((x>>2)*2 + (y>>2))*2 + (z>>2) (x, y, z in
+//                              0..7) set when all 64 voxels of that
+//                              sub-block share one value
 // with S = 2^ilog2 slots per axis per node, slot s = (sx*S + sy)*S + sz,
 // W = ceil(S^3 / 64) words per mask.  A root cell covers D = 8*S voxels.
 struct GridView {

@@ -72,7 +72,7 @@ struct Tree {
     const int32_t *root;
     const int32_t *slot;
     const uint64_t *leaves;
-    const uint64_t *sub;   // [leaves][2]: uniform 2^3 and 4^3 sub-blocks
+    const uint64_t *sub;   // [leaves]: uniform 4^3 sub-blocks
     int ilog2, S, NR;
 };
 
@@ -130,9 +130,9 @@ __device__ __forceinline__ Tree load_tree(const GridView &g, uint32_t *smem) {
 // VDB tree: the current cell is the largest uniform cell holding the current
 // voxel -- a root tile (D = 8*S voxels per axis), an internal-node tile
 // (D = 8) or a leaf voxel (D = 1); with kSub, inside a leaf also a uniform
-// 4^3 or 2^3 sub-block (D = 4, 2: all its voxels empty, or all occupied), so
-// that the cells nest as aligned cubes whose side halves level by level and a
-// step passes empty space by powers of two down to single voxels (Fig. 1).
+// 4^3 sub-block (D = 4: all its 64 voxels empty, or all occupied), so that
+// the cells nest as aligned cubes of 8S, 8, 4 and 1 voxels a side and a step
+// passes empty space by powers of two down to single voxels (Fig. 1).
 // The cell's exit is the first crossing of its far planes (for D = 1 the
 // ordinary voxel step).
 //
@@ -150,11 +150,13 @@ __device__ __forceinline__ Tree load_tree(const GridView &g, uint32_t *smem) {
 // and the walk moves on to the next voxel, so the tree only changes how
 // occupancy is looked up, not which cells are visited.
 //
-// kSub trades steps for dearer ones: on the object-scene workload it takes
-// about 30% fewer steps, but the cell size changes about four times as often
-// inside leaves, and each change recomputes all exits (and, going down,
-// re-locates the other axes and looks the cell up again), in some lane of
-// nearly every step of a wave.
+// kSub trades steps for dearer ones: it takes about a third fewer steps, but
+// the cell size changes more often inside leaves, and each change recomputes
+// all exits (and, going down, re-locates the other axes and looks the cell up
+// again), in some lane of most steps of a wave.  Only 4^3 sub-blocks are
+// cells: adding the 2^3 ones (D = 2) saves a few more steps but changes the
+// size about twice as often again, which costs more than it saves (object
+// walk 0.230 against 0.209 ms, four cascades the same).
 template <bool kTiles, bool kSub = false>
 struct VdbWalk {
     Tree t;
@@ -169,8 +171,7 @@ struct VdbWalk {
     bool occ;              // current cell occupied
     int lblk;              // cached leaf block (packed block coordinates), -1 if none
     int lbase;             // its first word in the leaf array
-    uint64_t lu2;          // its uniform 2^3 sub-blocks (Tree::sub word 0)
-    uint32_t lu4;          // its uniform 4^3 sub-blocks (Tree::sub word 1)
+    uint32_t lu4;          // its uniform 4^3 sub-blocks (its Tree::sub entry)
 
     // Size of the largest uniform cell holding voxel (v0, v1, v2) and its
     // occupancy.  A voxel in the cached leaf block (most voxel steps) needs
@@ -193,11 +194,7 @@ struct VdbWalk {
             if (!root_tile && !slot_tile) {
                 lblk = blk;
                 lbase = c * 8;
-                if (kSub) {
-                    const uint4 u = *reinterpret_cast<const uint4 *>(t.sub + 2 * c);
-                    lu2 = (uint64_t)u.y << 32 | u.x;
-                    lu4 = u.z;
-                }
+                if (kSub) lu4 = (uint32_t)t.sub[c];
             } else {
                 o = root_tile ? node == -2 : c == -2;
                 return kTiles ? (root_tile ? (8 << t.ilog2) : 8) : 1;
@@ -208,13 +205,9 @@ struct VdbWalk {
         const uint32_t half = bit < 32 ? (uint32_t)word : (uint32_t)(word >> 32);
         o = ((half >> (bit & 31)) & 1u) != 0;
         if (kSub) {
-            // a uniform sub-block takes the voxel's value: the largest one holding it is the cell
-            const int s2 = (((v0 >> 1) & 3) << 4) | (((v1 >> 1) & 3) << 2) | ((v2 >> 1) & 3);
+            // a uniform 4^3 sub-block takes the voxel's value and is the cell
             const int s4 = (((v0 >> 2) & 1) << 2) | (((v1 >> 2) & 1) << 1) | ((v2 >> 2) & 1);
-            const uint32_t h2 = s2 < 32 ? (uint32_t)lu2 : (uint32_t)(lu2 >> 32);
-            const bool u2 = ((h2 >> (s2 & 31)) & 1u) != 0;
-            const bool u4 = ((lu4 >> s4) & 1u) != 0;
-            D = u4 ? 4 : (u2 ? 2 : 1);
+            D = ((lu4 >> s4) & 1u) != 0 ? 4 : 1;
         }
         return D;
     }
@@ -682,7 +675,6 @@ __device__ __forceinline__ bool cursor_begin(typename CursorOf<kGrid>::type &c, 
         c.k0 = c.k1 = c.k2 = 0;
         c.lblk = -1;
         c.lbase = 0;
-        c.lu2 = 0;
         c.lu4 = 0;
         c.enter();
     }

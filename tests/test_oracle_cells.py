@@ -9,9 +9,9 @@ gives the count of every walk on grids built so that the cells are known:
 * hierarchical DDA (Sec. 2.3) on an all-empty or all-full grid: one root tile
   per root cell, D = 8 * 2^ilog2;
 * sub-leaf steps (Fig. 1: empty space passed by powers of two) on a grid that
-  is a checkerboard of 2^3 (4^3) blocks: every leaf is mixed and so is every
-  4^3 (8^3) block, but every 2^3 (4^3) block is uniform, so D = 2 (4); on a
-  checkerboard of single voxels nothing merges and the count is the dense one.
+  is a checkerboard of 4^3 blocks: every leaf is mixed, but every 4^3 block is
+  uniform, so D = 4; on checkerboards of single voxels or of 2^3 blocks no 4^3
+  block is uniform, nothing merges and the count is the dense one.
 
 Plus the ordering every grid must show: a sub-leaf walk visits no more cells
 than the hierarchical one, which visits no more than the dense one.
@@ -120,7 +120,7 @@ def test_subleaf_walk_on_block_checkerboards(e):
     dense = expected(rays, R, 1)
     # every 8^3 block is mixed, so the hierarchical walk steps voxel by voxel
     np.testing.assert_array_equal(cells(scene, rays, "hdda_branch", 1), dense)
-    np.testing.assert_array_equal(cells(scene, rays, "subleaf_branch", 1), expected(rays, R, e))
+    np.testing.assert_array_equal(cells(scene, rays, "subleaf_branch", 1), expected(rays, R, 4 if e == 4 else 1))
 
 
 @settings(max_examples=60, deadline=None, suppress_health_check=[HealthCheck.too_slow])
@@ -128,8 +128,8 @@ def test_subleaf_walk_on_block_checkerboards(e):
        blocky=st.booleans(), ilog2=st.sampled_from([1, 2]))
 def test_cell_counts_are_ordered(seed, R, p, blocky, ilog2):
     rng = np.random.default_rng(seed)
-    if blocky:   # uniform 2^3 blocks, so sub-leaf steps have something to merge
-        occ = np.repeat(np.repeat(np.repeat(rng.random((R // 2,) * 3) < p, 2, 0), 2, 1), 2, 2)
+    if blocky:   # uniform 4^3 blocks, so sub-leaf steps have something to merge
+        occ = np.repeat(np.repeat(np.repeat(rng.random((R // 4,) * 3) < p, 4, 0), 4, 1), 4, 2)
     else:
         occ = rng.random((R, R, R)) < p
     scene = oracle.Scene(occ.astype(np.uint8)[None], box1())
