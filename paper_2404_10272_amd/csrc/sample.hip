@@ -70,9 +70,12 @@ __device__ __forceinline__ void add_chunk_sums(int64_t ray, int32_t n, int64_t *
 // counts[i] = samples of ray i; nruns[i] = its occupied runs (kRunsLost: the
 // run pool ran dry, the traversal fill writes the ray); the runs themselves
 // go to the pool's slots and chunks; tile_sums[k] gains the counts of rays
-// k*kScanTile .. (k+1)*kScanTile-1.
+// k*kScanTile .. (k+1)*kScanTile-1.  Single-level walks ask for 7 waves per
+// SIMD (8 for the dense march): the prioritised long waves then share their
+// SIMD with more short ones (the compiler would otherwise settle at 6 once
+// the span is computed before the walk).
 template <int kGrid, bool kSkip, bool kLds, bool kL1>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kGrid == 0 && kL1 ? 8 : 1))) count_kernel(GridView g, const float *__restrict__ origins,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kL1 ? (kGrid == 0 ? 8 : 7) : 1))) count_kernel(GridView g, const float *__restrict__ origins,
                                                        const float *__restrict__ dirs, int64_t n_rays, Lattice lat,
                                                        int32_t *__restrict__ counts, int32_t *__restrict__ nruns,
                                                        RunPool pool, int image_width,
@@ -82,7 +85,28 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kGr
     Tree tree = reads_tree(kGrid) ? load_tree<kLds>(g, smem) : Tree{};
     const int64_t i = ray_of_thread((int64_t)blockIdx.x * kBlock + threadIdx.x, n_rays, image_width);
     int32_t n = 0;
-    if (i >= 0) {
+    if constexpr (kL1) {
+        // the span first, so the wave's priority can follow its longest ray
+        float o[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 0.f};
+        L1Span s{};
+        if (i >= 0) {
+            load_ray(origins, dirs, i, o, d);
+            s = l1_span(g, o, d, lat);
+        }
+        set_wave_priority(s.hit ? (fminf(s.X, lat.tmax) - fmaxf(s.E, lat.tmin)) *
+                                      (fabsf(d[0]) * g.geom[6] + fabsf(d[1]) * g.geom[7] + fabsf(d[2]) * g.geom[8])
+                                : 0.0f,
+                          g.R);
+        if (i >= 0) {
+            const CountCtx ctx{lat, pool};
+            CountVis vis = make_count_vis(i, pool);
+            if (s.hit) march_segment<kGrid, kSkip>(g, tree, 0, s.ray, s.E, s.X, lat, vis, ctx);
+            vis.finish(ctx);
+            n = vis.n;
+            counts[i] = n;
+            nruns[i] = vis.nr;
+        }
+    } else if (i >= 0) {
         float o[3], d[3];
         load_ray(origins, dirs, i, o, d);
         const CountCtx ctx{lat, pool};

@@ -697,6 +697,46 @@ __device__ __forceinline__ bool span_of(const GridView &g, int lev, const Ray &r
     return level_span(A0, A1, A2, E, X);
 }
 
+// A single-level ray before its walk: the reciprocal direction and the
+// grid's span (E, X]; hit is false for a ray with no samples to find (it
+// misses the grid, the span lies outside [t_min, t_max], t_min > t_max, or
+// the origin or direction is not finite).
+struct L1Span {
+    Ray ray;
+    float E, X;
+    bool hit;
+};
+
+__device__ __forceinline__ L1Span l1_span(const GridView &g, const float o[3], const float d[3], const Lattice &lat) {
+    L1Span s{};
+    bool ok = lat.tmin <= lat.tmax;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ok = ok && __builtin_isfinite(o[a]) && __builtin_isfinite(d[a]);
+    s.ray = Ray{o[0], o[1], o[2], d[0], d[1], d[2], __fdiv_rn(1.0f, d[0]), __fdiv_rn(1.0f, d[1]), __fdiv_rn(1.0f, d[2])};
+    s.hit = ok && span_of(g, 0, s.ray, s.E, s.X) && s.E < lat.tmax && s.X >= lat.tmin;
+    return s;
+}
+
+// Issue priority of a wave from the dense-step estimate of its longest ray:
+// sum over axes of |d_a| * len / h_a, with len its span's length inside
+// [t_min, t_max], against the grid's resolution R (a ray through the grid
+// crosses between R and 3R planes).  The waves of long rays walk longest --
+// on a camera looking at an object, the image's centre tiles run for the
+// whole launch while most waves end early -- so letting them issue first
+// when several waves of a SIMD are ready shortens the launch, and the short
+// waves fill the gaps.  The level is made wave-uniform (readfirstlane), so
+// the wave takes one scalar branch.  All 64 lanes must call it together.
+__device__ __forceinline__ void set_wave_priority(float nv, int R) {
+    if (!(nv >= 0.0f)) nv = 0.0f;
+#pragma unroll
+    for (int k = 32; k >= 1; k >>= 1) nv = fmaxf(nv, __shfl_xor(nv, k));
+    const float r = (float)R;
+    const int lvl = __builtin_amdgcn_readfirstlane(nv > 1.65f * r ? 3 : nv > 1.15f * r ? 2 : nv > 0.6f * r ? 1 : 0);
+    if (lvl == 3) __builtin_amdgcn_s_setprio(3);
+    else if (lvl == 2) __builtin_amdgcn_s_setprio(2);
+    else if (lvl == 1) __builtin_amdgcn_s_setprio(1);
+}
+
 // All samples of one ray, in increasing t.  The cascade boxes are nested
 // (checked when the grid is built), so level l holds exactly (E_l, X_l] and
 // these intervals nest.  With f the finest level the ray meets and
@@ -708,17 +748,16 @@ __device__ __forceinline__ bool span_of(const GridView &g, int lev, const Ray &r
 template <int kGrid, bool kSkip, bool kL1 = false, class Vis, class Ctx>
 __device__ __forceinline__ void trace_ray(const GridView &g, const Tree &tree, const float o[3], const float d[3],
                                           const Lattice &lat, Vis &vis, const Ctx &ctx) {
+    if (kL1) {
+        const L1Span s = l1_span(g, o, d, lat);
+        if (s.hit) march_segment<kGrid, kSkip>(g, tree, 0, s.ray, s.E, s.X, lat, vis, ctx);
+        return;
+    }
     if (!(lat.tmin <= lat.tmax)) return;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         if (!__builtin_isfinite(o[a]) || !__builtin_isfinite(d[a])) return;
     Ray ray{o[0], o[1], o[2], d[0], d[1], d[2], __fdiv_rn(1.0f, d[0]), __fdiv_rn(1.0f, d[1]), __fdiv_rn(1.0f, d[2])};
-    if (kL1) {
-        float E, X;
-        if (span_of(g, 0, ray, E, X) && E < lat.tmax && X >= lat.tmin)
-            march_segment<kGrid, kSkip>(g, tree, 0, ray, E, X, lat, vis, ctx);
-        return;
-    }
     const int L = g.L;
     int f = -1;
     for (int lev = 0; lev < L && f < 0; ++lev) {
