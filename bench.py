@@ -31,6 +31,9 @@ METRIC = "rays/s + samples/s, VDB+HDDA vs dense-OG march, 800×800 rays, sample-
 VARIANTS = ["vdb_other", "vdb_rows", "dense", "dense_skip", "dense_rows", "chessboard", "voxel", "voxel_other",
             "subleaf"]
 HBM_PEAK_GBS = 8000.0
+# MI355X: 256 CUs x 4 SIMDs at 2.4 GHz; a 64-lane wave's VALU instruction
+# takes 4 clocks on a 16-lane SIMD
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def parse():
@@ -516,14 +519,17 @@ def main():
     achieved = step_bytes / (sum_ms * 1e-3) / 1e9
 
     counters = None
+    issue = None
     tpath = os.path.join(ROOT, "profiles", "traffic_object800.json")
     if os.path.exists(tpath):
         try:
             rec = json.load(open(tpath))
             if rec.get("kernel_source_sha") == _kernel_sha():
                 counters = rec.get("bytes_per_launch", {})
+                issue = rec.get("issue_per_launch", {}).get("count_kernel")
         except Exception:
             counters = None
+            issue = None
     per_kernel = {}
     for k in kern_bytes:
         b, t = kern_bytes[k], kern_ms[k]
@@ -535,6 +541,18 @@ def main():
             per_kernel[k]["traffic"] = tr
             per_kernel[k]["traffic_over_algorithmic"] = tr / b if b else None
     traffic = sum(v.get("traffic", 0.0) for v in per_kernel.values()) if counters is not None else None
+    if issue is not None:
+        # the walk is bound by instruction issue, not HBM: its wave-level VALU
+        # instructions per launch (SQ_INSTS_VALU of the committed counter run
+        # of these sources) over its event-timed duration, against one VALU
+        # instruction per SIMD every 4 clocks (a 64-lane wave on 16-lane SIMDs)
+        v = issue["SQ_INSTS_VALU"]
+        achieved_i = v / (walk_ms * 1e-3)
+        per_kernel["count_kernel"]["issue"] = {
+            "bound": "valu_issue", "valu_wave_insts": v, "achieved": achieved_i, "peak": VALU_ISSUE_PEAK,
+            "unit": "wave instructions/s", "frac": achieved_i / VALU_ISSUE_PEAK,
+            "lane_utilisation": issue["SQ_THREAD_CYCLES_VALU"] / (64.0 * issue["SQ_ACTIVE_INST_VALU"]),
+            "salu_wave_insts": issue["SQ_INSTS_SALU"], "branch_wave_insts": issue["SQ_INSTS_BRANCH"]}
 
     line = {
         "metric": METRIC,
