@@ -339,6 +339,52 @@ def test_empty_batch_and_far_before_near(small):
     assert got["offsets"][-1] == 0
 
 
+def test_one_call_edge_cases(small, small_ref):
+    """The one-call pass on degenerate inputs: no rays, t_min > t_max, rays
+    that all miss the grid, a zero capacity, and 8x8-pixel tiles of an image
+    whose width (24, 63 or 65 pixels for the small workload's 4,096 rays)
+    leaves a partial last row and a ragged last column of tiles, whose lanes
+    past the image stay idle."""
+    g = gpu_grid("vdb", small.occ, small.boxes, small.ilog2)
+    step = api.make_step(small.step)
+
+    def one_call(o, d, near, far, cap, width=0):
+        n = o.shape[0]
+        sp = api.Sampler(g, n, near, far, step, "branch", image_width=width)
+        ids = torch.full((cap + 8,), -7, dtype=torch.int32, device="cuda")
+        t0 = torch.zeros(cap + 8, device="cuda")
+        t1 = torch.zeros(cap + 8, device="cuda")
+        offsets, overflow = sp.rays(o, d, ids[:cap], t0[:cap], t1[:cap])
+        torch.cuda.synchronize()
+        return offsets.cpu().numpy(), int(overflow.item()), ids, t0, t1
+
+    o = torch.from_numpy(small.origins).cuda()
+    d = torch.from_numpy(small.dirs).cuda()
+    # no rays
+    off, ovf, ids, _, _ = one_call(o[:0], d[:0], small.near, small.far, 0)
+    assert off.tolist() == [0] and ovf == 0
+    # t_min > t_max: every ray empty
+    off, ovf, ids, _, _ = one_call(o, d, small.far, small.near, 4)
+    assert not off.any() and ovf == 0 and bool((ids == -7).all())
+    # rays pointing away from the grid
+    off, ovf, ids, _, _ = one_call(o, -d, small.near, small.far, 4)
+    assert not off.any() and ovf == 0
+    # zero capacity: offsets still exact, overflow flagged, nothing written
+    S = int(small_ref["offsets"][-1])
+    off, ovf, ids, _, _ = one_call(o, d, small.near, small.far, 0)
+    np.testing.assert_array_equal(off, small_ref["offsets"])
+    assert ovf == (1 if S > 0 else 0) and bool((ids == -7).all())
+    # ragged 8x8 tiles: only which lane walks which ray changes
+    for width in (24, 63, 65):
+        off, ovf, ids, t0, t1 = one_call(o, d, small.near, small.far, S, width)
+        np.testing.assert_array_equal(off, small_ref["offsets"], err_msg=f"width {width}")
+        assert ovf == 0
+        np.testing.assert_array_equal(ids[:S].cpu().numpy(), small_ref["ray_ids"], err_msg=f"width {width}")
+        np.testing.assert_array_equal(t0[:S].cpu().numpy(), small_ref["t0"], err_msg=f"width {width}")
+        np.testing.assert_array_equal(t1[:S].cpu().numpy(), small_ref["t1"], err_msg=f"width {width}")
+        assert bool((ids[S:] == -7).all())
+
+
 def test_invalid_arguments_raise(small):
     g = gpu_grid("vdb", small.occ, small.boxes, small.ilog2)
     o = torch.from_numpy(small.origins).cuda()
