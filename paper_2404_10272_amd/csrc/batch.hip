@@ -39,7 +39,14 @@ struct SceneDesc {
     int64_t item0;   // its first queue item
     Lattice lat;
     int32_t width;   // image width for 8x8 tiling, 0 for none
+    int32_t lds;     // 1: the walk stages its tree's tables in LDS (they fit the launch's share)
 };
+
+// LDS a walk block may give a scene's staged tree tables: eight such blocks
+// fit a compute unit's 160 KiB (the autotuner tries up to eight per CU).
+// A 128^3 grid with 16^3-slot nodes needs 16 KiB and a few bytes; larger
+// trees are read from global memory.
+constexpr size_t kBatchTreeLds = 19 * 1024;
 
 // zeroes the queue head, the run-pool head and the lost-ray count
 // (queue[0], queue[1], queue[2])
@@ -64,40 +71,63 @@ __device__ __forceinline__ int scene_of_ray(const SceneDesc *scenes, int n, int6
     return 0;
 }
 
+// Threads tr in [r0, r1) of one queue item walk their rays with `tree`.
+template <bool kSkip>
+__device__ __forceinline__ void count_item(const SceneDesc *sc, const Tree &tree, int64_t r0, int64_t r1,
+                                           int32_t *__restrict__ counts, int32_t *__restrict__ nruns,
+                                           const RunPool &pool) {
+    const Lattice lat = sc->lat;
+    const GridView g = sc->g;
+    const CountCtx ctx{lat, pool};
+    for (int64_t tr = r0 + threadIdx.x; tr < r1; tr += kBlock) {
+        const int64_t r = ray_of_thread(tr, sc->n, sc->width);
+        if (r < 0) continue;
+        float o[3], d[3];
+        load_ray(sc->o, sc->d, r, o, d);
+        const int64_t gr = sc->first + r;
+        CountVis vis = make_count_vis(gr, pool);
+        // batches march a distance grid (kind 2) by its bitfield, as a dense grid
+        if (g.kind == 1) trace_ray<1, kSkip>(g, tree, o, d, lat, vis, ctx);
+        else trace_ray<0, kSkip>(g, tree, o, d, lat, vis, ctx);
+        vis.finish(ctx);
+        counts[gr] = vis.n;
+        nruns[gr] = vis.nr;
+    }
+}
+
 // Persistent: every workgroup loops pulling items until the queue runs dry,
-// so every wave reaches the exit once n_items items are handed out.
+// so every wave reaches the exit once n_items items are handed out.  The
+// queue hands out a scene's items one after another, so a block mostly takes
+// several items of one scene in a row: a scene whose tree fits (lds) has its
+// tables staged in LDS when a block's item is its first of that scene, and
+// read from there.  The block's barrier after taking an item means every
+// thread has finished the previous item before the tables are overwritten.
 template <bool kSkip>
 __global__ void __launch_bounds__(kBlock) batch_count_kernel(const SceneDesc *__restrict__ scenes, int n_scenes,
                                                              int64_t n_items, int chunk, int32_t *__restrict__ queue,
                                                              int32_t *__restrict__ counts,
                                                              int32_t *__restrict__ nruns, RunPool pool) {
+    extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int32_t s_item;
+    int staged = -1;   // scene whose tables are in smem (the same in every thread)
     while (true) {
         if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
         __syncthreads();
         const int64_t item = s_item;
         __syncthreads();
         if (item >= n_items) return;
-        const SceneDesc *sc = scenes + scene_of_item(scenes, n_scenes, item);
+        const int si = scene_of_item(scenes, n_scenes, item);
+        const SceneDesc *sc = scenes + si;
         const int64_t r0 = (item - sc->item0) * (int64_t)chunk;
         const int64_t r1 = min(r0 + (int64_t)chunk, sc->nt);
-        const Lattice lat = sc->lat;
-        const GridView g = sc->g;
-        const Tree tree = load_tree<false>(g, nullptr);
-        const CountCtx ctx{lat, pool};
-        for (int64_t tr = r0 + threadIdx.x; tr < r1; tr += kBlock) {
-            const int64_t r = ray_of_thread(tr, sc->n, sc->width);
-            if (r < 0) continue;
-            float o[3], d[3];
-            load_ray(sc->o, sc->d, r, o, d);
-            const int64_t gr = sc->first + r;
-            CountVis vis = make_count_vis(gr, pool);
-            // batches march a distance grid (kind 2) by its bitfield, as a dense grid
-            if (g.kind == 1) trace_ray<1, kSkip>(g, tree, o, d, lat, vis, ctx);
-            else trace_ray<0, kSkip>(g, tree, o, d, lat, vis, ctx);
-            vis.finish(ctx);
-            counts[gr] = vis.n;
-            nruns[gr] = vis.nr;
+        if (sc->lds) {
+            if (si != staged) {
+                stage_tree(sc->g, smem);
+                staged = si;
+            }
+            count_item<kSkip>(sc, tree_in_lds(sc->g, smem), r0, r1, counts, nruns, pool);
+        } else {
+            count_item<kSkip>(sc, load_tree<false>(sc->g, nullptr), r0, r1, counts, nruns, pool);
         }
     }
 }
@@ -176,6 +206,7 @@ struct ogv_batch {
     std::vector<SceneDesc> desc;   // host copy (item0 depends on the chunk)
     std::vector<int64_t> ray_base;
     int64_t n_total = 0, n_items = 0, n_tiles = 0;
+    size_t tree_lds = 0;   // dynamic LDS of the walk: the largest staged tree
     ogv_tune tune{0, 0};
     bool tuned = false;
     float tune_ms = 0.0f;
@@ -215,11 +246,11 @@ void enqueue_count(ogv_batch *b, const ogv_tune &t, hipStream_t s) {
     batch_reset_kernel<<<1, 64, 0, s>>>(b->queue);
     unsigned grid = (unsigned)std::max(1, b->n_cu * t.blocks_per_cu);
     if (b->variant == OGV_SKIP)
-        batch_count_kernel<true><<<grid, kBlock, 0, s>>>(b->desc_dev, b->n_scenes, b->n_items, t.chunk, b->queue,
-                                                         b->counts, b->nruns, b->pool);
+        batch_count_kernel<true><<<grid, kBlock, b->tree_lds, s>>>(b->desc_dev, b->n_scenes, b->n_items, t.chunk,
+                                                                   b->queue, b->counts, b->nruns, b->pool);
     else
-        batch_count_kernel<false><<<grid, kBlock, 0, s>>>(b->desc_dev, b->n_scenes, b->n_items, t.chunk, b->queue,
-                                                          b->counts, b->nruns, b->pool);
+        batch_count_kernel<false><<<grid, kBlock, b->tree_lds, s>>>(b->desc_dev, b->n_scenes, b->n_items, t.chunk,
+                                                                    b->queue, b->counts, b->nruns, b->pool);
 }
 
 hipError_t enqueue_pass(ogv_batch *b, int64_t *offsets, int64_t capacity, int32_t *ids, float *t0, float *t1,
@@ -384,6 +415,9 @@ extern "C" ogv_status ogv_batch_create(const ogv_scene *scenes, int32_t n, int32
         d.width = sc.image_width;
         d.nt = tiled_threads(sc.n_rays, sc.image_width);
         d.first = b->ray_base[i];
+        const size_t tb = d.g.kind == 1 ? tree_lds_bytes(d.g.L, d.g.NR, d.g.S) : 0;
+        d.lds = d.g.kind == 1 && tb <= kBatchTreeLds ? 1 : 0;
+        if (d.lds) b->tree_lds = std::max(b->tree_lds, tb);
         Lattice &L = d.lat;
         L.tmin = sc.near_t;
         L.tmax = sc.far_t;

@@ -98,23 +98,27 @@ __device__ __forceinline__ void stage_to_lds(int4 *dst, const int4 *__restrict__
     }
 }
 
-// Every thread of the block must call this (it synchronizes).  smem must be
-// 16-byte aligned; the slot table is (the build aligns every table to 256
-// bytes, and a table holds S^3 entries per root cell, a multiple of 4).
-template <bool kLds>
-__device__ __forceinline__ Tree load_tree(const GridView &g, uint32_t *smem) {
+// The tree's view with its slot and root tables at smem (slot table first,
+// then the root table: tree_lds_bytes), as stage_tree leaves them.  Node
+// slots exist for every root cell (the worst case the build sizes for).
+__device__ __forceinline__ Tree tree_in_lds(const GridView &g, uint32_t *smem) {
     Tree t;
     t.ilog2 = g.ilog2;
     t.S = g.S;
     t.NR = g.NR;
     t.leaves = g.leaves;
     t.sub = g.sub;
-    if (!kLds) {
-        t.root = g.root;
-        t.slot = g.slot;
-        return t;
-    }
-    // node slots exist for every root cell (the worst case the build sizes for)
+    const int ns = g.L * g.NR * g.NR * g.NR * g.S * g.S * g.S;
+    t.slot = (const int32_t *)smem;
+    t.root = (const int32_t *)smem + ns;
+    return t;
+}
+
+// Copies the slot and root tables to smem.  Every thread of the block must
+// call this (it synchronizes).  smem must be 16-byte aligned; the slot table
+// is (the build aligns every table to 256 bytes, and a table holds S^3
+// entries per root cell, a multiple of 4).
+__device__ __forceinline__ void stage_tree(const GridView &g, uint32_t *smem) {
     const int n_root = g.L * g.NR * g.NR * g.NR;
     const int ns = n_root * g.S * g.S * g.S;
     int32_t *slot = (int32_t *)smem;
@@ -122,8 +126,24 @@ __device__ __forceinline__ Tree load_tree(const GridView &g, uint32_t *smem) {
     stage_to_lds(reinterpret_cast<int4 *>(slot), reinterpret_cast<const int4 *>(g.slot), ns >> 2);
     for (int i = threadIdx.x; i < n_root; i += blockDim.x) root[i] = g.root[i];
     __syncthreads();
-    t.root = root;
-    t.slot = slot;
+}
+
+// The tree a walk reads: its tables staged in LDS (kLds; every thread of the
+// block must call this), or read from global memory.
+template <bool kLds>
+__device__ __forceinline__ Tree load_tree(const GridView &g, uint32_t *smem) {
+    if (kLds) {
+        stage_tree(g, smem);
+        return tree_in_lds(g, smem);
+    }
+    Tree t;
+    t.ilog2 = g.ilog2;
+    t.S = g.S;
+    t.NR = g.NR;
+    t.leaves = g.leaves;
+    t.sub = g.sub;
+    t.root = g.root;
+    t.slot = g.slot;
     return t;
 }
 
