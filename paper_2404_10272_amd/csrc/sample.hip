@@ -73,9 +73,16 @@ __device__ __forceinline__ void add_chunk_sums(int64_t ray, int32_t n, int64_t *
 // k*kScanTile .. (k+1)*kScanTile-1.  Single-level walks ask for 7 waves per
 // SIMD (8 for the dense march): the prioritised long waves then share their
 // SIMD with more short ones (the compiler would otherwise settle at 6 once
-// the span is computed before the walk).
+// the span is computed before the walk).  The cascade walks of the Alg. 1
+// loop over the dense grid, the hierarchical and the sub-leaf steps ask for
+// 5 (the compiler would settle at 4 with about 100 VGPRs; 5 spills up to 9
+// registers and measured faster, 6 spills 46 to 78).
+constexpr int count_waves_per_eu(int kGrid, bool kSkip, bool kL1) {
+    return kL1 ? (kGrid == 0 ? 8 : 7) : (!kSkip && (kGrid == 0 || kGrid == 1 || kGrid == 4) ? 5 : 1);
+}
+
 template <int kGrid, bool kSkip, bool kLds, bool kL1>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kL1 ? (kGrid == 0 ? 8 : 7) : 1))) count_kernel(GridView g, const float *__restrict__ origins,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(count_waves_per_eu(kGrid, kSkip, kL1)))) count_kernel(GridView g, const float *__restrict__ origins,
                                                        const float *__restrict__ dirs, int64_t n_rays, Lattice lat,
                                                        int32_t *__restrict__ counts, int32_t *__restrict__ nruns,
                                                        RunPool pool, int image_width,
