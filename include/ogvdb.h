@@ -69,8 +69,9 @@ typedef int32_t ogv_status;
  * not with OGV_VOXEL) makes the hierarchical steps go on below the leaf
  * level: a uniform 4^3 sub-block of a leaf (all 64 voxels empty or all
  * occupied) is passed in one step, so empty space is skipped by powers of two
- * (root tile, 8^3 tile, 4^3 sub-block) down to single voxels (Fig. 1).  A sampling call rejects either on any
- * other grid with OGV_ERR_INVALID; batches take OGV_BRANCH or OGV_SKIP only.
+ * (root tile, 8^3 tile, 4^3 sub-block) down to single voxels (Fig. 1).  A
+ * sampling call rejects either on any other grid with OGV_ERR_INVALID;
+ * batches take OGV_BRANCH or OGV_SKIP only.
  * Every variant gives identical samples. */
 #define OGV_BRANCH 0
 #define OGV_SKIP 1

@@ -106,10 +106,10 @@ __device__ __forceinline__ void count_item(const SceneDesc *sc, const Tree &tree
 // with 108 VGPRs; 5 spills 20 registers and measured 4.8% faster on the
 // 16-scene pass, 6 spills 311).
 template <bool kSkip>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kSkip ? 1 : 5))) batch_count_kernel(const SceneDesc *__restrict__ scenes, int n_scenes,
-                                                             int64_t n_items, int chunk, int32_t *__restrict__ queue,
-                                                             int32_t *__restrict__ counts,
-                                                             int32_t *__restrict__ nruns, RunPool pool) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kSkip ? 1 : 5)))
+batch_count_kernel(const SceneDesc *__restrict__ scenes, int n_scenes, int64_t n_items, int chunk,
+                   int32_t *__restrict__ queue, int32_t *__restrict__ counts, int32_t *__restrict__ nruns,
+                   RunPool pool) {
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int32_t s_item;
     int staged = -1;   // scene whose tables are in smem (the same in every thread)

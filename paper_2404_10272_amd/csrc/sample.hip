@@ -82,12 +82,10 @@ constexpr int count_waves_per_eu(int kGrid, bool kSkip, bool kL1) {
 }
 
 template <int kGrid, bool kSkip, bool kLds, bool kL1>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(count_waves_per_eu(kGrid, kSkip, kL1)))) count_kernel(GridView g, const float *__restrict__ origins,
-                                                       const float *__restrict__ dirs, int64_t n_rays, Lattice lat,
-                                                       int32_t *__restrict__ counts, int32_t *__restrict__ nruns,
-                                                       RunPool pool, int image_width,
-                                                       int64_t *__restrict__ tile_sums,
-                                                       int64_t *__restrict__ chunk_sums) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(count_waves_per_eu(kGrid, kSkip, kL1))))
+count_kernel(GridView g, const float *__restrict__ origins, const float *__restrict__ dirs, int64_t n_rays,
+             Lattice lat, int32_t *__restrict__ counts, int32_t *__restrict__ nruns, RunPool pool, int image_width,
+             int64_t *__restrict__ tile_sums, int64_t *__restrict__ chunk_sums) {
     extern __shared__ __align__(16) uint32_t smem[];
     Tree tree = reads_tree(kGrid) ? load_tree<kLds>(g, smem) : Tree{};
     const int64_t i = ray_of_thread((int64_t)blockIdx.x * kBlock + threadIdx.x, n_rays, image_width);

@@ -170,7 +170,7 @@ __device__ __forceinline__ Tree load_tree(const GridView &g, uint32_t *smem) {
 // and the walk moves on to the next voxel, so the tree only changes how
 // occupancy is looked up, not which cells are visited.
 //
-// kSub trades steps for dearer ones: it takes about a third fewer steps, but
+// kSub trades steps for dearer ones: it takes a fifth to a quarter fewer steps, but
 // the cell size changes more often inside leaves, and each change recomputes
 // all exits (and, going down, re-locates the other axes and looks the cell up
 // again), in some lane of most steps of a wave.  Only 4^3 sub-blocks are
@@ -1054,9 +1054,9 @@ __device__ __forceinline__ void expand_chunk(ExpandLds &sh, const float2 *s_lat,
         // outputs meet one of its windows (w = part, part + kExpandParts, ...),
         // and only those rays' run counts and first run slots are read: the
         // windows are tiled by such rays, and the other parts write the rest.
-        // This cuts the expansion's reads by more than half (the three-call form, whose
-        // offsets come from memory, measured slower with it and keeps every
-        // ray).
+        // This cuts the expansion's reads by more than half.  The three-call
+        // form, whose offsets come from memory, measured slower with it and
+        // keeps every ray.
         mine = in && off_next > off;
         if (mine) {
             const int64_t wa = ((off >> 2) - G0) / kExpandGroups, wb = (((off_next - 1) >> 2) - G0) / kExpandGroups;
