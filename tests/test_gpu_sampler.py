@@ -385,6 +385,47 @@ def test_one_call_edge_cases(small, small_ref):
         assert bool((ids[S:] == -7).all())
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_one_call_random_layouts(seed):
+    """The one-call pass on random grids (resolution, occupancy, internal
+    node size), random ray counts, random image widths (the 8x8-tile lane
+    layout, ragged or not) and random capacities (exact, short, zero),
+    for the VDB, sub-leaf and dense walks, against the oracle."""
+    rng = np.random.default_rng(1000 + seed)
+    R = int(rng.choice([16, 24, 40, 64]))
+    p = float(rng.choice([0.02, 0.1, 0.3, 0.6]))
+    occ = (rng.random((1, R, R, R)) < p).astype(np.uint8)
+    if seed % 2:   # blocky: uniform 4^3 and 8^3 regions, so tiles and sub-blocks occur
+        k = 4
+        coarse = (rng.random((1, R // k + 1, R // k + 1, R // k + 1)) < p).astype(np.uint8)
+        occ = np.repeat(np.repeat(np.repeat(coarse, k, 1), k, 2), k, 3)[:, :R, :R, :R].copy()
+    boxes = np.asarray([[-1, -1, -1, 1, 1, 1]], np.float32)
+    n = int(rng.integers(1, 20000))
+    o, d = scenes.random_rays(n, rng, -1.8, 1.8)
+    step = oracle.make_step("const", dt=float(rng.choice([0.01, 0.023])))
+    ref = oracle.sample_rays(oracle.Scene(occ, boxes), o, d, 0.0, 5.0, step, "dense_branch", threads=16)
+    S = int(ref["offsets"][-1])
+    od, dd = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
+    width = int(rng.choice([0, int(rng.integers(1, 200))]))
+    ilog2 = int(rng.choice([1, 2]))
+    for kind, variant in (("vdb", "branch"), ("vdb", "subleaf_branch"), ("dense", "branch")):
+        g = gpu_grid(kind, occ, boxes, ilog2)
+        sp = api.Sampler(g, n, 0.0, 5.0, step, variant, image_width=width)
+        for cap in (S, S // 3, 0):
+            ids = torch.full((cap + 4,), -7, dtype=torch.int32, device="cuda")
+            t0 = torch.zeros(cap + 4, device="cuda")
+            t1 = torch.zeros(cap + 4, device="cuda")
+            offsets, overflow = sp.rays(od, dd, ids[:cap], t0[:cap], t1[:cap])
+            torch.cuda.synchronize()
+            what = f"seed {seed} R {R} n {n} width {width} {kind} {variant} cap {cap}"
+            np.testing.assert_array_equal(offsets.cpu().numpy(), ref["offsets"], err_msg=what)
+            assert int(overflow.item()) == (1 if cap < S else 0), what
+            np.testing.assert_array_equal(ids[:cap].cpu().numpy(), ref["ray_ids"][:cap], err_msg=what)
+            np.testing.assert_array_equal(t0[:cap].cpu().numpy(), ref["t0"][:cap], err_msg=what)
+            np.testing.assert_array_equal(t1[:cap].cpu().numpy(), ref["t1"][:cap], err_msg=what)
+            assert bool((ids[cap:] == -7).all()), what
+
+
 def test_invalid_arguments_raise(small):
     g = gpu_grid("vdb", small.occ, small.boxes, small.ilog2)
     o = torch.from_numpy(small.origins).cuda()
