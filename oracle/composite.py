@@ -97,3 +97,59 @@ def composite_loss_grad(C, target):
     target = np.asarray(target, np.float64)
     diff = C - target
     return float(np.mean(diff * diff)), 2.0 * diff / diff.size
+
+
+# ---------------------------------------------------------------------------
+# The same quantities for every ray at once, in array form, so that a whole
+# image of packed samples can be checked: per-ray sums become segment sums
+# over the ray each sample belongs to.  T before sample i is exp of minus the
+# sum of the ray's earlier tau (the loop form multiplies the factors; the two
+# agree to FP64 rounding), and the suffix sum over later samples is the ray's
+# total less the inclusive prefix.  offsets[0] must be 0.
+
+def _ray_of_sample(offsets):
+    offsets = np.asarray(offsets, dtype=np.int64)
+    counts = np.diff(offsets)
+    return offsets, counts, np.repeat(np.arange(counts.size), counts)
+
+
+def _earlier_sum(x, offsets, ray):
+    """For each sample, the sum of x over the earlier samples of its ray."""
+    cs = np.cumsum(x, axis=0)
+    before = np.concatenate([np.zeros((1,) + x.shape[1:]), cs])[offsets[:-1]]
+    return cs - x - before[ray]
+
+
+def composite_forward_all(offsets, t0, t1, sigma, rgb):
+    """composite_forward over every ray in array form: (C[N,3], A[N], T_final[N])."""
+    offsets, counts, ray = _ray_of_sample(offsets)
+    n_rays = counts.size
+    tau = np.asarray(sigma, np.float64) * (np.asarray(t1, np.float64) - np.asarray(t0, np.float64))
+    rgb = np.asarray(rgb, np.float64).reshape(-1, 3)
+    w = np.exp(-_earlier_sum(tau, offsets, ray)) * (-np.expm1(-tau))
+    C = np.stack([np.bincount(ray, weights=w * rgb[:, k], minlength=n_rays) for k in range(3)], axis=1)
+    A = np.bincount(ray, weights=w, minlength=n_rays)
+    Tf = np.exp(-np.bincount(ray, weights=tau, minlength=n_rays))
+    return C, A, Tf
+
+
+def composite_backward_all(offsets, t0, t1, sigma, rgb, g_C, g_A):
+    """composite_backward over every ray in array form: (dL/dsigma[S], dL/drgb[S,3])."""
+    offsets, counts, ray = _ray_of_sample(offsets)
+    n_rays = counts.size
+    dt = np.asarray(t1, np.float64) - np.asarray(t0, np.float64)
+    tau = np.asarray(sigma, np.float64) * dt
+    rgb = np.asarray(rgb, np.float64).reshape(-1, 3)
+    g_C = np.asarray(g_C, np.float64).reshape(-1, 3)
+    g_A = np.asarray(g_A, np.float64).reshape(-1)
+    earlier = _earlier_sum(tau, offsets, ray)
+    T_after = np.exp(-(earlier + tau))
+    T_final = np.exp(-np.bincount(ray, weights=tau, minlength=n_rays))
+    w = np.exp(-earlier) * (-np.expm1(-tau))
+    wc = w[:, None] * rgb
+    total = np.stack([np.bincount(ray, weights=wc[:, k], minlength=n_rays) for k in range(3)], axis=1)
+    later = total[ray] - (_earlier_sum(wc, offsets, ray) + wc)   # sum_{k>i} w_k c_k
+    dC_dtau = T_after[:, None] * rgb - later
+    d_sigma = dt * (np.einsum("ij,ij->i", g_C[ray], dC_dtau) + g_A[ray] * T_final[ray])
+    d_rgb = w[:, None] * g_C[ray]
+    return d_sigma, d_rgb

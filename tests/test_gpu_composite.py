@@ -1,5 +1,6 @@
-"""Fused composite forward/backward on the GPU against the FP64 oracle and
-FP64 central finite differences, on the object workload's packed samples.
+"""Fused composite forward/backward on the GPU against the FP64 oracle (every
+ray of the object workload's packed samples, and the loop form on sampled
+rays) and FP64 central finite differences (sampled rays).
 
 Tolerance (per ray, separately for d_sigma and d_rgb and for the forward
 outputs): ||g - g_ref||_inf <= 1e-4 * max(||g_ref||_inf, tiny).
@@ -57,6 +58,45 @@ def test_forward_backward_against_oracle(packed):
         ds, drgb = oracle.composite_backward(sub_off, t0[a:b], t1[a:b], sigma[a:b], rgb[a:b], gC, [0.0])
         assert np.abs(gs[a:b] - ds).max() <= TOL * max(np.abs(ds).max(), 1e-30), r
         assert np.abs(gr[a:b] - drgb).max() <= TOL * max(np.abs(drgb).max(), 1e-30), r
+
+
+def _ray_max(x, off_h, counts):
+    """Per nonempty ray, the largest |x| over its samples (x: [S] or [S, 3])."""
+    x = np.abs(np.asarray(x, np.float64)).reshape(x.shape[0], -1).max(axis=1)
+    return np.maximum.reduceat(x, off_h[:-1][counts > 0])
+
+
+def test_all_rays_against_oracle(packed):
+    """Every ray of the workload (640,000 rays, 25.8 M samples): the forward
+    outputs, and the backward pass for a random upstream gradient of both
+    outputs, against the oracle's array form, to the same per-ray bound."""
+    out, sigma, rgb, _ = packed
+    off = out["offsets"]
+    N = off.numel() - 1
+    off_h = off.cpu().numpy()
+    counts = np.diff(off_h)
+    t0 = out["t0"].cpu().numpy()
+    t1 = out["t1"].cpu().numpy()
+    sig = torch.from_numpy(sigma).cuda()
+    col = torch.from_numpy(rgb).cuda()
+    rng = np.random.default_rng(4004)
+    g_rgb = rng.normal(size=(N, 3)).astype(np.float32)
+    g_a = rng.normal(size=N).astype(np.float32)
+    C, A = api.composite_forward(off, out["t0"], out["t1"], sig, col)
+    d_s, d_c = api.composite_backward(off, out["t0"], out["t1"], sig, col, torch.from_numpy(g_rgb).cuda(),
+                                      torch.from_numpy(g_a).cuda())
+    torch.cuda.synchronize()
+    C_h, A_h = C.cpu().numpy().astype(np.float64), A.cpu().numpy().astype(np.float64)
+    Cr, Ar, _ = oracle.composite_forward_all(off_h, t0, t1, sigma, rgb)
+    bad = np.abs(C_h - Cr).max(axis=1) > TOL * np.maximum(np.abs(Cr).max(axis=1), 1e-30)
+    assert not bad.any(), (int(bad.sum()), np.nonzero(bad)[0][:5])
+    bad = np.abs(A_h - Ar) > TOL * np.maximum(np.abs(Ar), 1e-30)
+    assert not bad.any(), (int(bad.sum()), np.nonzero(bad)[0][:5])
+    ds, dc = oracle.composite_backward_all(off_h, t0, t1, sigma, rgb, g_rgb, g_a)
+    for got, ref, what in ((d_s.cpu().numpy(), ds, "d_sigma"), (d_c.cpu().numpy(), dc, "d_rgb")):
+        err = _ray_max(got.astype(np.float64) - ref, off_h, counts)
+        scale = np.maximum(_ray_max(ref, off_h, counts), 1e-30)
+        assert (err <= TOL * scale).all(), (what, int((err > TOL * scale).sum()), float((err / scale).max()))
 
 
 def test_gradient_against_fp64_finite_differences(packed):

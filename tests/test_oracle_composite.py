@@ -9,10 +9,17 @@ import math
 import numpy as np
 import pytest
 
-from oracle import composite_forward, composite_backward, composite_loss_grad
+from oracle import (composite_forward, composite_backward, composite_loss_grad, composite_forward_all,
+                    composite_backward_all)
+
+# the loop form (ray by ray, sample by sample) and the array form (every ray at
+# once, for checks over a whole image) face the same pins
+FORMS = {"loop": (composite_forward, composite_backward), "array": (composite_forward_all, composite_backward_all)}
 
 
-def test_one_sample_closed_form():
+@pytest.mark.parametrize("form", FORMS)
+def test_one_sample_closed_form(form):
+    composite_forward, composite_backward = FORMS[form]
     # dt = 1, sigma = ln 2: alpha = w = A = 1/2, C = c/2, dA/dsigma = 1/2, dC/dsigma = c/2
     c = np.array([[0.2, 0.5, 0.9]])
     C, A, Tf = composite_forward([0, 1], [0.0], [1.0], [math.log(2.0)], c)
@@ -29,7 +36,9 @@ def test_one_sample_closed_form():
         np.testing.assert_allclose(drgb[0], 0.5 * g[0], rtol=1e-15)
 
 
-def test_two_samples_closed_form():
+@pytest.mark.parametrize("form", FORMS)
+def test_two_samples_closed_form(form):
+    composite_forward, composite_backward = FORMS[form]
     # w = (1/2, 1/4), A = 3/4; dA/dsigma_0 = dA/dsigma_1 = 1/4;
     # dC/dsigma_0 = c0/2 - c1/4, dC/dsigma_1 = c1/4
     c = np.array([[0.3, 0.6, 0.1], [0.8, 0.2, 0.4]])
@@ -47,7 +56,9 @@ def test_two_samples_closed_form():
         np.testing.assert_allclose(ds, [0.5 * c[0, ch] - 0.25 * c[1, ch], 0.25 * c[1, ch]], rtol=1e-13, atol=1e-16)
 
 
-def test_weights_sum_to_opacity_and_empty_rays():
+@pytest.mark.parametrize("form", FORMS)
+def test_weights_sum_to_opacity_and_empty_rays(form):
+    composite_forward, composite_backward = FORMS[form]
     rng = np.random.default_rng(0)
     counts = np.array([0, 3, 0, 7, 1])
     off = np.concatenate([[0], np.cumsum(counts)])
@@ -62,8 +73,10 @@ def test_weights_sum_to_opacity_and_empty_rays():
     assert A[0] == 0 and A[2] == 0 and np.all(C[[0, 2]] == 0)
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("seed", [1, 2, 3])
-def test_gradient_matches_central_differences(seed):
+def test_gradient_matches_central_differences(seed, form):
+    composite_forward, composite_backward = FORMS[form]
     rng = np.random.default_rng(seed)
     counts = rng.integers(0, 12, size=6)
     off = np.concatenate([[0], np.cumsum(counts)])
@@ -96,7 +109,9 @@ def test_gradient_matches_central_differences(seed):
             assert abs(fd - drgb[i, ch]) <= 1e-7 * max(1.0, abs(drgb).max())
 
 
-def test_opacity_gradient_matches_central_differences():
+@pytest.mark.parametrize("form", FORMS)
+def test_opacity_gradient_matches_central_differences(form):
+    composite_forward, composite_backward = FORMS[form]
     rng = np.random.default_rng(9)
     off = np.array([0, 5])
     t0 = np.cumsum(rng.uniform(0.01, 0.05, 5))
@@ -111,3 +126,27 @@ def test_opacity_gradient_matches_central_differences():
         sm[i] -= eps
         fd = (composite_forward(off, t0, t1, sp, rgb)[1][0] - composite_forward(off, t0, t1, sm, rgb)[1][0]) / (2 * eps)
         assert abs(fd - ds[i]) < 1e-8
+
+
+def test_forms_agree_on_an_image():
+    # uneven rays (empty ones included) of dense and sparse media; the two forms
+    # differ only in FP64 rounding order
+    rng = np.random.default_rng(17)
+    counts = rng.integers(0, 300, size=200)
+    counts[rng.choice(200, 20, replace=False)] = 0
+    off = np.concatenate([[0], np.cumsum(counts)])
+    S = int(off[-1])
+    t0 = rng.uniform(2.0, 6.0, S)
+    t1 = t0 + 0.005
+    sig = np.exp(rng.normal(size=S)) * rng.choice([0.1, 10.0, 200.0], S)
+    rgb = rng.random((S, 3))
+    gC = rng.normal(size=(200, 3))
+    gA = rng.normal(size=200)
+    a = composite_forward(off, t0, t1, sig, rgb)
+    b = composite_forward_all(off, t0, t1, sig, rgb)
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(y, x, rtol=1e-11, atol=1e-15)
+    a = composite_backward(off, t0, t1, sig, rgb, gC, gA)
+    b = composite_backward_all(off, t0, t1, sig, rgb, gC, gA)
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(y, x, rtol=1e-9, atol=1e-12 * np.abs(x).max())
