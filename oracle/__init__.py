@@ -20,7 +20,7 @@ import numpy as np
 
 from .composite import (composite_forward, composite_backward, composite_loss_grad,  # noqa: F401
                         composite_forward_all, composite_backward_all)
-from .render import blob_field, render_blobs  # noqa: F401
+from .render import blob_field, render_blobs, render_blobs_all  # noqa: F401
 from .distance import chessboard_distance, chessboard_distance_brute  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))

@@ -12,10 +12,13 @@ available here, so a synthetic field of K Gaussian blobs stands in for it:
 
 Each sample is taken at its interval midpoint, x_i = o + d (t0_i + t1_i) / 2,
 and the ray is composited with composite_forward (emission-absorption).
+render_blobs_all does the same for every ray at once (the field evaluated in
+chunks of samples, the composite in array form), for checks over a whole
+image.
 """
 import numpy as np
 
-from .composite import composite_forward
+from .composite import composite_forward, composite_forward_all
 
 
 def blob_field(points, centres, radii, densities, colours):
@@ -52,4 +55,26 @@ def render_blobs(offsets, origins, dirs, t0, t1, centres, radii, densities, colo
         sigma, colour = blob_field(pts, centres, radii, densities, colours)
         Cr, Ar, _ = composite_forward([0, b - a], t0[a:b], t1[a:b], sigma, colour)
         C[j], A[j] = Cr[0], Ar[0]
+    return C, A
+
+
+def render_blobs_all(offsets, origins, dirs, t0, t1, centres, radii, densities, colours, chunk=1 << 21):
+    """Pixel (C[N,3], A[N]) of every ray, float64: render_blobs in array form.
+    offsets[0] must be 0; samples past offsets[-1] are ignored."""
+    offsets = np.asarray(offsets, np.int64)
+    counts = np.diff(offsets)
+    ray = np.repeat(np.arange(counts.size), counts)
+    S = ray.shape[0]
+    o = np.asarray(origins, np.float64).reshape(-1, 3)
+    d = np.asarray(dirs, np.float64).reshape(-1, 3)
+    t0 = np.asarray(t0, np.float64)[:S]
+    t1 = np.asarray(t1, np.float64)[:S]
+    sigma = np.empty(S)
+    colour = np.empty((S, 3))
+    for a in range(0, S, chunk):
+        b = min(S, a + chunk)
+        mid = 0.5 * (t0[a:b] + t1[a:b])
+        pts = o[ray[a:b]] + d[ray[a:b]] * mid[:, None]
+        sigma[a:b], colour[a:b] = blob_field(pts, centres, radii, densities, colours)
+    C, A, _ = composite_forward_all(offsets, t0, t1, sigma, colour)
     return C, A

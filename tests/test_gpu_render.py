@@ -1,5 +1,6 @@
 """Fused blob-field rendering on the GPU against the FP64 oracle, on the
-800x800 object workload's packed samples.
+800x800 object workload's packed samples: every ray (array form) and a
+sample of rays (ray-by-ray form).
 
 Tolerance (per ray, as for the composite): ||C - C_ref||_inf <= 1e-4 *
 max(||C_ref||_inf, tiny), and the same for the opacity.
@@ -39,6 +40,17 @@ def test_render_matches_oracle(rendered):
     for j, r in enumerate(rays):
         assert np.abs(C[r] - Cr[j]).max() <= TOL * max(np.abs(Cr[j]).max(), 1e-30), (r, C[r], Cr[j])
         assert abs(A[r] - Ar[j]) <= TOL * max(abs(Ar[j]), 1e-30), (r, A[r], Ar[j])
+
+
+def test_render_matches_oracle_on_every_ray(rendered):
+    w, out, blobs, C, A = rendered
+    off = out["offsets"].cpu().numpy()
+    Cr, Ar = oracle.render_blobs_all(off, w.origins, w.dirs, out["t0"].cpu().numpy(), out["t1"].cpu().numpy(),
+                                      *blobs)
+    bad = np.abs(C - Cr).max(axis=1) > TOL * np.maximum(np.abs(Cr).max(axis=1), 1e-30)
+    assert not bad.any(), (int(bad.sum()), np.nonzero(bad)[0][:5])
+    bad = np.abs(A - Ar) > TOL * np.maximum(np.abs(Ar), 1e-30)
+    assert not bad.any(), (int(bad.sum()), np.nonzero(bad)[0][:5])
 
 
 def test_rays_without_samples_are_black(rendered):
