@@ -199,6 +199,33 @@ def cascades_side(api, torch, scenes, steps, warmup):
     return out
 
 
+def cameras_side(api, torch, scenes, w, vdb, dense, variant, primary, steps, warmup):
+    """The object grid seen from four more seeded cameras (same grid, same
+    lattice): the one-call step with the VDB + hierarchical DDA and with the
+    dense march per view, and the medians over the five views (the primary
+    one included).  primary: (vdb ms, dense ms, samples) of the headline view."""
+    import numpy as np
+    views = [{"seed": "primary", "vdb_ms": primary[0], "dense_ms": primary[1], "samples": primary[2]}]
+    for seed, o_h, d_h in scenes.object_extra_cameras(4, *w.image):
+        o = torch.from_numpy(o_h).cuda()
+        d = torch.from_numpy(d_h).cuda()
+        tv = Timed(api, torch, vdb, w, o, d, variant, w.image[0])
+        td = Timed(api, torch, dense, w, o, d, "branch", w.image[0])
+        assert tv.S == td.S, "samplers disagree on the sample count"
+        views.append({"seed": seed, "vdb_ms": tv.run(steps, warmup)[0], "dense_ms": td.run(steps, warmup)[0],
+                      "samples": tv.S})
+        del tv, td
+    N = w.n_rays
+    for v in views:
+        v["rays_per_s"] = N / (v["vdb_ms"] * 1e-3)
+        v["samples_per_s"] = v["samples"] / (v["vdb_ms"] * 1e-3)
+        v["speedup_vs_dense"] = v["dense_ms"] / v["vdb_ms"]
+    med = lambda k: float(np.median([v[k] for v in views]))
+    return {"views": views, "median_rays_per_s": med("rays_per_s"), "median_samples_per_s": med("samples_per_s"),
+            "median_speedup_vs_dense": med("speedup_vs_dense"), "median_vdb_ms": med("vdb_ms"),
+            "median_dense_ms": med("dense_ms")}
+
+
 def render_side(api, torch, scenes, hdda, w, steps):
     """End-to-end frame on the 800x800 object workload: the sampler's step
     (count + scan + fill) then one fused pass that evaluates a 12-blob
@@ -597,6 +624,10 @@ def main():
     line["hbm_floor"]["fill_vs_write_only"] = line["hbm_floor"]["write_only_ms"] / scan_fill_ms
     line.update(compare)
     if not args.no_side:
+        dense_ms = compare["dense"]["ms_per_step"] if "dense" in compare else \
+            Timed(api, torch, dense, w, o, d, "branch", W).run(min(args.steps, 20), 2)[0]
+        line["cameras"] = cameras_side(api, torch, scenes, w, vdb, dense, args.variant, (ms, dense_ms, S),
+                                       min(args.steps, 20), 2)
         line["composite"] = composite_side(api, torch, scenes, hdda, N, min(args.steps, 20))
         line["batched"] = batched_side(api, torch, scenes, min(args.steps, 10))
         line["cascades"] = cascades_side(api, torch, scenes, min(args.steps, 10), 2)

@@ -230,6 +230,18 @@ def object_scene(seed=SEED_BASE["object"], width=800, height=800):
                     {"kind": "const", "dt": 5e-3, "cone": 0.0, "dt_min": 0.0}, 4, (width, height))
 
 
+def object_extra_cameras(k=4, width=800, height=800):
+    """k more views of the object scene's grid, camera j drawn like the
+    primary one from its own generator (seed SEED_BASE["object"] + j, j = 1..k):
+    a list of (seed, origins, dirs)."""
+    out = []
+    for j in range(1, k + 1):
+        seed = SEED_BASE["object"] + j
+        o, d = object_camera_rays(width, height, np.random.default_rng(seed))
+        out.append((seed, o, d))
+    return out
+
+
 def unbounded(seed=SEED_BASE["unbounded"], width=1280, height=832, R=128):
     rng = np.random.default_rng(seed)
     fracs = [0.15, 0.10, 0.06, 0.03]

@@ -202,6 +202,30 @@ def test_object_workload_800x800(obj, obj_ref, variant):
         assert_same(got, obj_ref, f"object {variant} (image width {width})")
 
 
+@pytest.mark.parametrize("view", range(4))
+def test_object_extra_views(obj, view):
+    """The four more camera views the benchmark times beside the headline one
+    (same grid and lattice), every ray, with the one-call path and the 8x8
+    pixel-tile lanes it times, VDB + hierarchical DDA and dense march."""
+    seed, o, d = scenes.object_extra_cameras(4, *obj.image)[view]
+    scene = oracle.Scene(obj.occ, obj.boxes)
+    ref = oracle.sample_rays(scene, o, d, obj.near, obj.far, obj.step, "dense_branch", ilog2=obj.ilog2)
+    S = int(ref["offsets"][-1])
+    o_d, d_d = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
+    for kind in ("vdb", "dense"):
+        g = gpu_grid(kind, obj.occ, obj.boxes, obj.ilog2)
+        sp = api.Sampler(g, obj.n_rays, obj.near, obj.far, obj.step, "branch", image_width=obj.image[0])
+        ids = torch.empty(S, dtype=torch.int32, device="cuda")
+        t0 = torch.empty(S, dtype=torch.float32, device="cuda")
+        t1 = torch.empty(S, dtype=torch.float32, device="cuda")
+        offsets, overflow = sp.rays(o_d, d_d, ids, t0, t1)
+        torch.cuda.synchronize()
+        assert int(overflow.item()) == 0
+        got = {"offsets": offsets.cpu().numpy(), "ray_ids": ids.cpu().numpy(), "t0": t0.cpu().numpy(),
+               "t1": t1.cpu().numpy()}
+        assert_same(got, ref, f"view {seed} {kind}")
+
+
 def test_object_workload_capacity_mode(obj, obj_ref):
     """The one-call capacity path the benchmark times: exact capacity, then a
     too-small capacity (overflow flagged, nothing written past it)."""
