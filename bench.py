@@ -388,11 +388,13 @@ def cpu_baseline(obj_stride=1, unb_stride=2):
     """The oracle as it stands (count + fill of every ray, OpenMP over rays),
     timed on the host cores: the plain dense DDA (O2) and the VDB +
     hierarchical DDA (O3), both in the Alg. 1 loop the GPU bench times, on
-    the object workload (every `obj_stride`-th ray) and the four-cascade
-    workload (every `unb_stride`-th ray), each the median of 3 runs; O3 and O2
-    on one thread over every 64th object ray; brute force (O1) on all of the
-    64x64 small workload.  `value` is O3 on the object workload.  Also the
-    cells per ray that the dense, hierarchical and sub-leaf walks visit."""
+    the object workload (every `obj_stride`-th ray), the four-cascade
+    workload (every `unb_stride`-th ray) and the 16-scene batch (every 4th /
+    32nd ray of each scene), each the median of 3 runs; O3 and O2 on one
+    thread over every 64th object ray; brute force (O1) on all of the 64x64
+    small workload and a seeded 4,096-ray subset of the object workload.
+    `value` is O3 on the object workload.  Also the cells per ray that the
+    dense, hierarchical and sub-leaf walks visit."""
     import numpy as np
     import oracle
     from paper_2404_10272_amd import scenes
@@ -400,30 +402,49 @@ def cpu_baseline(obj_stride=1, unb_stride=2):
     methods = {}
     spent = 0.0
 
-    def leg(name, w, stride, method, nthreads):
+    def leg(name, ws, sel, method, nthreads, sample):
+        # ws: the workloads the leg walks (one, or the batch's scenes); sel
+        # picks each one's rays (a slice or an index array)
         nonlocal spent
-        scene = oracle.Scene(w.occ, w.boxes)
-        if method.startswith("hdda"):
-            scene.vdb(w.ilog2)   # built outside the timed region, as on the GPU
-        o = np.ascontiguousarray(w.origins[::stride])
-        d = np.ascontiguousarray(w.dirs[::stride])
-        run = lambda: oracle.sample_rays(scene, o, d, w.near, w.far, w.step, method, ilog2=w.ilog2,
-                                         threads=nthreads)
-        med, out = _median3(run)
-        spent += 3 * med
-        methods[name] = {"value": o.shape[0] / med, "unit": "rays/s", "median_s": med, "rays": int(o.shape[0]),
-                         "samples": int(out["offsets"][-1]), "threads": nthreads, "method": method,
-                         "sample": f"{w.name} workload, every {stride}th ray"}
+        prepared = []
+        for w in ws:
+            scene = oracle.Scene(w.occ, w.boxes)
+            if method.startswith("hdda"):
+                scene.vdb(w.ilog2)   # built outside the timed region, as on the GPU
+            prepared.append((w, scene, np.ascontiguousarray(w.origins[sel]), np.ascontiguousarray(w.dirs[sel])))
 
+        def run():
+            return sum(int(oracle.sample_rays(sc, o, d, w.near, w.far, w.step, method, ilog2=w.ilog2,
+                                              threads=nthreads)["offsets"][-1]) for w, sc, o, d in prepared)
+
+        med, S = _median3(run)
+        spent += 3 * med
+        n = sum(p[2].shape[0] for p in prepared)
+        methods[name] = {"value": n / med, "unit": "rays/s", "median_s": med, "rays": n, "samples": S,
+                         "threads": nthreads, "method": method, "sample": sample}
+
+    every = lambda name, k: f"{name} workload, " + ("every ray" if k == 1 else f"one ray in {k}")
     obj = scenes.workload("object")
-    leg("object_hdda", obj, obj_stride, "hdda_branch", threads)
-    leg("object_dense_dda", obj, obj_stride, "dense_branch", threads)
-    leg("object_hdda_1thread", obj, 64 * obj_stride, "hdda_branch", 1)
-    leg("object_dense_dda_1thread", obj, 64 * obj_stride, "dense_branch", 1)
+    leg("object_hdda", [obj], slice(None, None, obj_stride), "hdda_branch", threads, every("object", obj_stride))
+    leg("object_dense_dda", [obj], slice(None, None, obj_stride), "dense_branch", threads,
+        every("object", obj_stride))
+    leg("object_hdda_1thread", [obj], slice(None, None, 64 * obj_stride), "hdda_branch", 1,
+        every("object", 64 * obj_stride))
+    leg("object_dense_dda_1thread", [obj], slice(None, None, 64 * obj_stride), "dense_branch", 1,
+        every("object", 64 * obj_stride))
+    pick = np.sort(np.random.default_rng(2000).choice(obj.n_rays, 4096, replace=False))
+    leg("object_brute_force", [obj], pick, "brute", threads, "object workload, a seeded 4,096-ray subset")
     unb = scenes.workload("unbounded")
-    leg("unbounded_hdda", unb, unb_stride, "hdda_branch", threads)
-    leg("unbounded_dense_dda", unb, unb_stride, "dense_branch", threads)
-    leg("small_brute_force", scenes.workload("small"), 1, "brute", threads)
+    leg("unbounded_hdda", [unb], slice(None, None, unb_stride), "hdda_branch", threads,
+        every("unbounded", unb_stride))
+    leg("unbounded_dense_dda", [unb], slice(None, None, unb_stride), "dense_branch", threads,
+        every("unbounded", unb_stride))
+    leg("small_brute_force", [scenes.workload("small")], slice(None), "brute", threads, "small workload, every ray")
+    bat = scenes.batched()
+    leg("batched_hdda", bat, slice(None, None, 32), "hdda_branch", threads,
+        "16-scene batch, one ray in 32 of each scene")
+    leg("batched_dense_dda", bat, slice(None, None, 4), "dense_branch", threads,
+        "16-scene batch, one ray in 4 of each scene")
     # cells a ray's walk visits, per traversal (every 16th ray): what the walk
     # kernels' time scales with
     cells = {}
@@ -441,7 +462,7 @@ def cpu_baseline(obj_stride=1, unb_stride=2):
         pass
     head = methods["object_hdda"]
     return {"value": head["value"], "unit": "rays/s", "cores": threads, "kind": "oracle",
-            "sample": f"object workload, every {obj_stride}th ray ({head['rays']} rays, {head['samples']} samples), "
+            "sample": f"{head['sample']} ({head['rays']} rays, {head['samples']} samples), "
                       f"VDB + hierarchical DDA (Alg. 1 loop), count + fill, median of 3 runs on {threads} threads; "
                       f"{spent:.1f} s of oracle time over all legs",
             "methods": methods, "cells_per_ray": cells,
@@ -485,6 +506,16 @@ def main():
     W = w.image[0]
     hdda = Timed(api, torch, vdb, w, o, d, args.variant, W)
     ms, walk_ms, scan_ms, fill_ms = hdda.run(args.steps, args.warmup)
+    # the Python wrapper end to end (count, the total read back to the host, outputs allocated, fill),
+    # host wall clock: a secondary figure beside the event-timed call
+    wall = []
+    for _ in range(12):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        api.sample_rays(vdb, o, d, w.near, w.far, api.make_step(w.step), args.variant, image_width=W)
+        torch.cuda.synchronize()
+        wall.append((time.perf_counter() - t) * 1e3)
+    wrapper_wall_ms = sorted(wall[2:])[len(wall[2:]) // 2]
     # in-place asynchronous refresh of the tree (same occupancy, so the grid is unchanged)
     refresh_ms = time_events(torch, lambda: vdb.refresh(occ), 10, 2)
     compare = {}
@@ -607,6 +638,7 @@ def main():
                                "fill_ms": fill_ms, "count_scan_ms": count_ms},
                 "rays_per_s": N / (ms * 1e-3),
                 "bytes": G, "leaves": vinfo["n_leaves"], "build_ms": build_ms, "refresh_ms": refresh_ms,
+                "wrapper_wall_ms": wrapper_wall_ms,
                 "step_stats": hdda.step_stats},
         "step_bytes": step_bytes,
         "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
