@@ -652,6 +652,10 @@ def main():
                      "dominant_kernel": max(kern_ms, key=kern_ms.get),
                      "stages_ms": {"walk": walk_ms, "scan_and_fill": scan_fill_ms}},
     }
+    pr = torch.cuda.get_device_properties(0)
+    line["device"] = {k: getattr(pr, k, None) for k in (
+        "name", "gcnArchName", "multi_processor_count", "warp_size", "total_memory", "L2_cache_size",
+        "shared_memory_per_block", "regs_per_multiprocessor", "max_threads_per_multi_processor")}
     line["hbm_floor"] = hbm_floor(torch, S, min(args.steps, 20))
     line["hbm_floor"]["fill_vs_write_only"] = line["hbm_floor"]["write_only_ms"] / scan_fill_ms
     line.update(compare)
