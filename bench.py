@@ -389,8 +389,8 @@ def cpu_baseline(obj_stride=1, unb_stride=2):
     timed on the host cores: the plain dense DDA (O2) and the VDB +
     hierarchical DDA (O3), both in the Alg. 1 loop the GPU bench times, on
     the object workload (every `obj_stride`-th ray), the four-cascade
-    workload (every `unb_stride`-th ray) and the 16-scene batch (every 4th /
-    32nd ray of each scene), each the median of 3 runs; O3 and O2 on one
+    workload (every `unb_stride`-th ray) and the 16-scene batch (O2 on one
+    ray in 4 of each scene, O3 on one in 32), each the median of 3 runs; O3 and O2 on one
     thread over every 64th object ray; brute force (O1) on all of the 64x64
     small workload and a seeded 4,096-ray subset of the object workload.
     `value` is O3 on the object workload.  Also the cells per ray that the
