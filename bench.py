@@ -675,10 +675,13 @@ def main():
 
 
 def _kernel_sha():
+    """Hash of what the step's kernels are built from: their sources and the
+    build script that holds the compiler flags."""
     import hashlib
     h = hashlib.sha256()
-    for f in ["sample.hip", "trace.hpp", "geometry.hpp", "scan.hpp", "internal.hpp"]:
-        with open(os.path.join(ROOT, "paper_2404_10272_amd", "csrc", f), "rb") as fh:
+    for f in ["csrc/sample.hip", "csrc/trace.hpp", "csrc/geometry.hpp", "csrc/scan.hpp", "csrc/internal.hpp",
+              "build.py"]:
+        with open(os.path.join(ROOT, "paper_2404_10272_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

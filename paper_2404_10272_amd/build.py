@@ -16,8 +16,12 @@ LIB = os.path.join(HERE, "libogvdb.so")
 SOURCES = ["grid.hip", "sample.hip", "composite.hip", "batch.hip"]
 ARCH = os.environ.get("OGV_OFFLOAD_ARCH", "gfx950")
 
+# Optimisation level per source: the sampler's walk measured about 2% faster
+# at -O2 than at -O3 (the same samples); the rest stays at -O3.
+OPT = {"sample.hip": "-O2"}
+
 FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
     "-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt", "-fno-gpu-flush-denormals-to-zero",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
@@ -26,7 +30,7 @@ FLAGS = [
 
 def _compile(src, verbose):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ["hipcc", *FLAGS, OPT.get(src, "-O3"), "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
