@@ -102,9 +102,10 @@ __device__ __forceinline__ void count_item(const SceneDesc *sc, const Tree &tree
 // tables staged in LDS when a block's item is its first of that scene, and
 // read from there.  The block's barrier after taking an item means every
 // thread has finished the previous item before the tables are overwritten.
-// The Alg. 1 loop asks for 5 waves per SIMD (the compiler would settle at 4
-// with 108 VGPRs; 5 spills 20 registers and measured 4.8% faster on the
-// 16-scene pass, 6 spills 311).
+// The Alg. 1 loop asks for at least 5 waves per SIMD (at -O3 the compiler
+// would settle at 4 with 108 VGPRs; 5 spilled 20 registers and measured 4.8%
+// faster on the 16-scene pass).  This file's -O1 build fits the walk in 80
+// VGPRs with no spills, six waves per SIMD.
 template <bool kSkip>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kSkip ? 1 : 5)))
 batch_count_kernel(const SceneDesc *__restrict__ scenes, int n_scenes, int64_t n_items, int chunk,

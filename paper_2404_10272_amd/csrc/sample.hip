@@ -70,15 +70,18 @@ __device__ __forceinline__ void add_chunk_sums(int64_t ray, int32_t n, int64_t *
 // counts[i] = samples of ray i; nruns[i] = its occupied runs (kRunsLost: the
 // run pool ran dry, the traversal fill writes the ray); the runs themselves
 // go to the pool's slots and chunks; tile_sums[k] gains the counts of rays
-// k*kScanTile .. (k+1)*kScanTile-1.  Single-level walks ask for 7 waves per
-// SIMD (8 for the dense march): the prioritised long waves then share their
-// SIMD with more short ones (the compiler would otherwise settle at 6 once
-// the span is computed before the walk).  The cascade walks of the Alg. 1
-// loop over the dense grid, the hierarchical and the sub-leaf steps ask for
-// 5 (the compiler would settle at 4 with about 100 VGPRs; 5 spills up to 9
-// registers and measured faster, 6 spills 46 to 78).
+// k*kScanTile .. (k+1)*kScanTile-1.  Single-level walks of the Alg. 1 loop
+// ask for 7 waves per SIMD (8 for the dense march): the prioritised long
+// waves then share their SIMD with more short ones (the compiler would
+// otherwise settle at 6 once the span is computed before the walk).  The
+// single-level Alg. 2 walks over the tree ask for 5: their nested loops hold
+// more live values, and at 7 they spill about 40 registers.  The cascade
+// walks of the Alg. 1 loop over the dense grid, the hierarchical and the
+// sub-leaf steps ask for 5 (83 to 87 VGPRs, no spills; the compiler would
+// settle at 4).  Register counts are those of this file's -O1 build.
 constexpr int count_waves_per_eu(int kGrid, bool kSkip, bool kL1) {
-    return kL1 ? (kGrid == 0 ? 8 : 7) : (!kSkip && (kGrid == 0 || kGrid == 1 || kGrid == 4) ? 5 : 1);
+    return kL1 ? (kGrid == 0 ? 8 : kSkip ? 5 : 7)
+               : (!kSkip && (kGrid == 0 || kGrid == 1 || kGrid == 4) ? 5 : 1);
 }
 
 template <int kGrid, bool kSkip, bool kLds, bool kL1>

@@ -847,8 +847,9 @@ constexpr int kExpandGroups = 2048;   // 4-output groups per owner window
 constexpr int kExpandParts = 4;       // blocks sharing one chunk's windows
 // Waves per SIMD asked of the expansion kernels: six blocks of 256 lanes per CU
 // (LDS allows six).  At the register budget this leaves (80 VGPRs) the
-// constant-step expansion keeps its loops free of spills; only the rarely
-// taken lost-ray traversal and growing-step path spill.  An expansion block
+// expansion keeps its loops free of spills; only the rarely taken lost-ray
+// traversal spills (the -O1 build; at -O2 the growing-step path spilled as
+// well).  An expansion block
 // spends much of its life waiting on loads and barriers while the other
 // blocks' stores fill HBM, so residency is what keeps the writes flowing.
 constexpr int kExpandWaves = 6;
