@@ -679,8 +679,8 @@ def _kernel_sha():
     build script that holds the compiler flags."""
     import hashlib
     h = hashlib.sha256()
-    for f in ["csrc/sample.hip", "csrc/trace.hpp", "csrc/geometry.hpp", "csrc/scan.hpp", "csrc/internal.hpp",
-              "build.py"]:
+    for f in ["csrc/sample.hip", "csrc/count.hpp", "csrc/trace.hpp", "csrc/geometry.hpp", "csrc/scan.hpp",
+              "csrc/internal.hpp", "build.py"]:
         with open(os.path.join(ROOT, "paper_2404_10272_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
