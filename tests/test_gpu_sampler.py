@@ -481,6 +481,35 @@ def test_voxel_steps_only_on_vdb_grids(small):
             sp.count(o, d)
 
 
+def test_two_batches_in_flight(obj, obj_ref):
+    """Consecutive one-call steps alternating between two streams, each with
+    its own sampler workspace and outputs and one grid shared read-only, as
+    the benchmark's whole-job figure runs them: every stream's samples equal
+    the oracle's, for the VDB walk and the dense march."""
+    o = torch.from_numpy(np.ascontiguousarray(obj.origins)).cuda()
+    d = torch.from_numpy(np.ascontiguousarray(obj.dirs)).cuda()
+    S = int(obj_ref["offsets"][-1])
+    for kind in ("vdb", "dense"):
+        g = gpu_grid(kind, obj.occ, obj.boxes, obj.ilog2)
+        streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
+        sps = [api.Sampler(g, obj.n_rays, obj.near, obj.far, obj.step, "branch", image_width=obj.image[0])
+               for _ in streams]
+        outs = [(torch.full((S,), -1, dtype=torch.int32, device="cuda"),
+                 torch.full((S,), float("nan"), device="cuda"), torch.full((S,), float("nan"), device="cuda"))
+                for _ in streams]
+        torch.cuda.synchronize()
+        for k in range(6):
+            j = k % 2
+            with torch.cuda.stream(streams[j]):
+                sps[j].rays(o, d, *outs[j], stream=streams[j])
+        torch.cuda.synchronize()
+        for j in range(2):
+            got = {"offsets": sps[j].offsets.cpu().numpy(), "ray_ids": outs[j][0].cpu().numpy(),
+                   "t0": outs[j][1].cpu().numpy(), "t1": outs[j][2].cpu().numpy()}
+            assert_same(got, obj_ref, f"{kind} stream {j}")
+            assert int(sps[j].overflow.item()) == 0
+
+
 def test_determinism(obj):
     g = gpu_grid("vdb", obj.occ, obj.boxes, obj.ilog2)
     a = gpu_sample(g, obj.origins, obj.dirs, obj.near, obj.far, obj.step, "skip", voxel_ids=False)
