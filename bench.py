@@ -222,18 +222,21 @@ def composite_side(api, torch, scenes, hdda, N, steps):
             "backward_GBps": bb / (bwd * 1e-3) / 1e9, "samples": S}
 
 
-def cascades_side(api, torch, scenes, steps, warmup):
+def cascades_side(api, torch, scenes, steps, warmup, pipe=True):
     """Four nested 128^3 cascades over [-2^k, 2^k]^3, growing step (cone 1/256,
     dt_min 1e-3, near 0.05, far 1e3), 1280x832 rays from inside the scene:
-    count + scan + fill with the VDB + hierarchical DDA and with the dense march."""
+    count + scan + fill with the VDB + hierarchical DDA and with the dense march,
+    each also with two batches in flight (`pipelined`) unless pipe is false."""
     w = scenes.workload("unbounded")
     occ = torch.from_numpy(w.occ).cuda()
     o = torch.from_numpy(w.origins).cuda()
     d = torch.from_numpy(w.dirs).cuda()
     out = {"rays": w.n_rays, "levels": int(w.occ.shape[0])}
     vdb = api.build_vdb(occ, w.boxes, w.ilog2)
+    dense = api.build_dense(occ, w.boxes)
+    ref = None
     for name, grid, variant in (("vdb", vdb, "branch"), ("vdb_subleaf", vdb, "subleaf_branch"),
-                                ("dense", api.build_dense(occ, w.boxes), "branch")):
+                                ("dense", dense, "branch")):
         t = Timed(api, torch, grid, w, o, d, variant, w.image[0])
         ms, walk, scan, fill = t.run(steps, warmup)
         N, S, G = w.n_rays, t.S, grid.info()["bytes"]
@@ -242,7 +245,16 @@ def cascades_side(api, torch, scenes, steps, warmup):
                      "three_call": {"ms_per_step": t.three_call_ms, "scan_ms": scan, "fill_ms": fill},
                      "rays_per_s": N / (ms * 1e-3), "samples_per_s": S / (ms * 1e-3), "samples": S,
                      "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        if ref is None:
+            ref = t
         del t
+    if pipe:
+        pv = pipelined(api, torch, vdb, w, o, d, "branch", w.image[0], ref, steps, warmup)
+        pd = pipelined(api, torch, dense, w, o, d, "branch", w.image[0], ref, steps, warmup)
+        out["pipelined"] = {"streams": 2, "ms_per_step": pv, "rays_per_s": w.n_rays / (pv * 1e-3),
+                            "dense_ms_per_step": pd, "dense_rays_per_s": w.n_rays / (pd * 1e-3),
+                            "speedup_vs_dense": pd / pv}
+    del ref
     out["speedup_vs_dense"] = out["dense"]["ms_per_step"] / out["vdb"]["ms_per_step"]
     out["subleaf_speedup_vs_dense"] = out["dense"]["ms_per_step"] / out["vdb_subleaf"]["ms_per_step"]
     return out
@@ -731,7 +743,8 @@ def main():
                                        min(args.steps, 20), 2)
         line["composite"] = composite_side(api, torch, scenes, hdda, N, min(args.steps, 20))
         line["batched"] = batched_side(api, torch, scenes, min(args.steps, 10))
-        line["cascades"] = cascades_side(api, torch, scenes, min(args.steps, 10), 2)
+        line["cascades"] = cascades_side(api, torch, scenes, min(args.steps, 10), 2,
+                                         pipe=not (args.primary_only or args.no_pipeline))
         line["render"] = render_side(api, torch, scenes, hdda, w, min(args.steps, 20))
         line["refresh"] = refresh_side(api, torch, scenes, min(args.steps, 20))
     if not args.no_cpu:
