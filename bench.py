@@ -309,9 +309,11 @@ def render_side(api, torch, scenes, hdda, w, steps):
             "samples": S}
 
 
-def batched_side(api, torch, scenes, steps):
+def batched_side(api, torch, scenes, steps, pipe=True):
     """16 scenes (grids 64^3..256^3, 2-20 % occupied, 64^2..1024^2 rays):
-    one graph-captured batched pass vs 16 sequential single-scene calls."""
+    one graph-captured batched pass vs 16 sequential single-scene calls, and
+    (unless pipe is false) two graph-captured passes in flight on two streams,
+    each batch with its own workspace and outputs (`pipelined`)."""
     ws = scenes.batched()
     gs = []
     for w in ws:
@@ -345,7 +347,41 @@ def batched_side(api, torch, scenes, steps):
 
     seq_ms = time_events(torch, sequential, steps, 2)
     N = info["n_rays"]
+    pipelined_rec = None
+    if pipe:
+        b2 = api.Batch(gs, "branch", tune=(info["chunk"], info["blocks_per_cu"]))
+        out2 = (torch.empty(S, dtype=torch.int32, device="cuda"), torch.empty(S, device="cuda"),
+                torch.empty(S, device="cuda"))
+        cur = torch.cuda.current_stream()
+        streams = [cur, torch.cuda.Stream()]
+        runs = [(batch, (ids, t0, t1)), (b2, out2)]
+
+        def go(k):
+            j = k % 2
+            with torch.cuda.stream(streams[j]):
+                runs[j][0].launch(*runs[j][1], graph=True, stream=streams[j])
+
+        for k in range(4):
+            go(k)
+        torch.cuda.synchronize()
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(cur)
+        streams[1].wait_event(a)
+        for k in range(2 * steps):
+            go(k)
+        last = torch.cuda.Event()
+        last.record(streams[1])
+        cur.wait_event(last)
+        e.record(cur)
+        torch.cuda.synchronize()
+        pms = a.elapsed_time(e) / (2 * steps)
+        assert torch.equal(batch.offsets, b2.offsets) and all(torch.equal(x, y) for x, y in zip((ids, t0, t1), out2)), \
+            "the two in-flight batched passes disagree"
+        pipelined_rec = {"streams": 2, "ms_per_pass": pms, "rays_per_s": N / (pms * 1e-3),
+                         "speedup_vs_sequential": seq_ms / pms}
+        b2.close()
     return {"scenes": len(ws), "rays": N, "samples": S, "graph_ms": graph_ms, "eager_ms": eager_ms,
+            "pipelined": pipelined_rec,
             "sequential_ms": seq_ms, "rays_per_s": N / (graph_ms * 1e-3),
             "sequential_rays_per_s": N / (seq_ms * 1e-3), "speedup_vs_sequential": seq_ms / graph_ms,
             "tune": {"chunk": info["chunk"], "blocks_per_cu": info["blocks_per_cu"], "tuned": info["tuned"]}}
@@ -742,7 +778,8 @@ def main():
         line["cameras"] = cameras_side(api, torch, scenes, w, vdb, dense, args.variant, (ms, dense_ms, S),
                                        min(args.steps, 20), 2)
         line["composite"] = composite_side(api, torch, scenes, hdda, N, min(args.steps, 20))
-        line["batched"] = batched_side(api, torch, scenes, min(args.steps, 10))
+        line["batched"] = batched_side(api, torch, scenes, min(args.steps, 10),
+                                       pipe=not (args.primary_only or args.no_pipeline))
         line["cascades"] = cascades_side(api, torch, scenes, min(args.steps, 10), 2,
                                          pipe=not (args.primary_only or args.no_pipeline))
         line["render"] = render_side(api, torch, scenes, hdda, w, min(args.steps, 20))
