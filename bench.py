@@ -5,9 +5,9 @@ the 800x800-ray object-scene workload (128^3 grid, 6 % occupied): per-ray
 counts, their exclusive scan, and the fill of the packed (ray id, t0, t1)
 samples, inputs resident in HBM.  The dense-grid DDA marcher (the plain
 method) is timed with the same protocol on the same rays.  `value` is the
-VDB sampler's rays/s over K back-to-back steps with two batches in flight
-(consecutive steps alternate between two streams, each with its own
-workspace and outputs; `pipelined`); `latency` holds the same call timed
+VDB sampler's rays/s over K back-to-back steps with three batches in flight
+(consecutive steps take turns on three streams, each with its own workspace
+and outputs; `pipelined`); `latency` holds the same call timed
 step by step on one stream, which the rooflines use.  --primary-only and
 --no-pipeline time the single stream only (then `value` is its rate).
 
@@ -35,6 +35,9 @@ METRIC = "rays/s + samples/s, VDB+HDDA vs dense-OG march, 800×800 rays, sample-
 VARIANTS = ["vdb_other", "vdb_rows", "dense", "dense_skip", "dense_rows", "chessboard", "voxel", "voxel_other",
             "subleaf"]
 HBM_PEAK_GBS = 8000.0
+# batches in flight for the whole-job figures (streams of the default priority): three measured
+# 0.199-0.200 ms a step on the object workload, two 0.210-0.218, four 0.211
+IN_FLIGHT = 3
 # MI355X: 256 CUs x 4 SIMDs at 2.4 GHz; a 64-lane wave's VALU instruction
 # takes 4 clocks on a 16-lane SIMD
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
@@ -56,7 +59,7 @@ def parse():
                    help="comma list of the comparison samplers to time beside the headline (default: all of "
                         + ", ".join(VARIANTS) + ")")
     p.add_argument("--no-pipeline", action="store_true",
-                   help="time the headline on one stream only (no two-stream whole-job figure)")
+                   help="time the headline on one stream only (no whole-job figure with batches in flight)")
     p.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                    help="first run a plain device copy of MIB MiB (3 times), to calibrate HBM byte counters")
     return p.parse_args()
@@ -145,6 +148,20 @@ class Timed:
         return total_ms / steps, stage[0], stage[1], stage[2]
 
 
+_EXTRA_STREAMS = []
+
+
+def extra_streams(torch, n):
+    """n streams of the default priority besides the current one, created once
+    and reused by every phase that keeps batches in flight, so each phase runs
+    on the same hardware queues (streams map onto a few hardware queues in
+    creation order, and one that shares the current stream's queue is
+    serialized behind it)."""
+    while len(_EXTRA_STREAMS) < n:
+        _EXTRA_STREAMS.append(torch.cuda.Stream())
+    return _EXTRA_STREAMS[:n]
+
+
 def pipelined(api, torch, grid, w, o, d, variant, image_width, ref, steps, warmup, n_streams=2):
     """Whole-job throughput with n_streams batches in flight: consecutive
     steps alternate between n_streams streams of the default priority, each
@@ -157,7 +174,7 @@ def pipelined(api, torch, grid, w, o, d, variant, image_width, ref, steps, warmu
     Returns ms per step; every stream's offsets and samples must equal ref's
     (the single-stream headline call's)."""
     cur = torch.cuda.current_stream()
-    streams = [cur] + [torch.cuda.Stream() for _ in range(n_streams - 1)]
+    streams = [cur] + extra_streams(torch, n_streams - 1)
     ts = [Timed(api, torch, grid, w, o, d, variant, image_width) for _ in range(n_streams)]
 
     def go(k):
@@ -226,7 +243,7 @@ def cascades_side(api, torch, scenes, steps, warmup, pipe=True):
     """Four nested 128^3 cascades over [-2^k, 2^k]^3, growing step (cone 1/256,
     dt_min 1e-3, near 0.05, far 1e3), 1280x832 rays from inside the scene:
     count + scan + fill with the VDB + hierarchical DDA and with the dense march,
-    each also with two batches in flight (`pipelined`) unless pipe is false."""
+    each also with IN_FLIGHT batches in flight (`pipelined`) unless pipe is false."""
     w = scenes.workload("unbounded")
     occ = torch.from_numpy(w.occ).cuda()
     o = torch.from_numpy(w.origins).cuda()
@@ -249,9 +266,9 @@ def cascades_side(api, torch, scenes, steps, warmup, pipe=True):
             ref = t
         del t
     if pipe:
-        pv = pipelined(api, torch, vdb, w, o, d, "branch", w.image[0], ref, steps, warmup)
-        pd = pipelined(api, torch, dense, w, o, d, "branch", w.image[0], ref, steps, warmup)
-        out["pipelined"] = {"streams": 2, "ms_per_step": pv, "rays_per_s": w.n_rays / (pv * 1e-3),
+        pv = pipelined(api, torch, vdb, w, o, d, "branch", w.image[0], ref, steps, warmup, IN_FLIGHT)
+        pd = pipelined(api, torch, dense, w, o, d, "branch", w.image[0], ref, steps, warmup, IN_FLIGHT)
+        out["pipelined"] = {"streams": IN_FLIGHT, "ms_per_step": pv, "rays_per_s": w.n_rays / (pv * 1e-3),
                             "dense_ms_per_step": pd, "dense_rays_per_s": w.n_rays / (pd * 1e-3),
                             "speedup_vs_dense": pd / pv}
     del ref
@@ -353,7 +370,7 @@ def batched_side(api, torch, scenes, steps, pipe=True):
         out2 = (torch.empty(S, dtype=torch.int32, device="cuda"), torch.empty(S, device="cuda"),
                 torch.empty(S, device="cuda"))
         cur = torch.cuda.current_stream()
-        streams = [cur, torch.cuda.Stream()]
+        streams = [cur] + extra_streams(torch, 1)
         runs = [(batch, (ids, t0, t1)), (b2, out2)]
 
         def go(k):
@@ -650,16 +667,16 @@ def main():
         del timed
     count_ms = walk_ms + scan_ms
     N, S = w.n_rays, hdda.S
-    # whole-job throughput with two batches in flight, for the VDB sampler and
+    # whole-job throughput with IN_FLIGHT batches in flight, for the VDB sampler and
     # the dense march alike (both checked sample for sample against the headline)
     pipe = None
     if not (args.primary_only or args.no_pipeline):
-        pv = pipelined(api, torch, vdb, w, o, d, args.variant, W, hdda, args.steps, args.warmup)
-        pd = pipelined(api, torch, dense, w, o, d, "branch", W, hdda, args.steps, args.warmup)
-        pipe = {"streams": 2, "ms_per_step": pv, "rays_per_s": N / (pv * 1e-3), "samples_per_s": S / (pv * 1e-3),
+        pv = pipelined(api, torch, vdb, w, o, d, args.variant, W, hdda, args.steps, args.warmup, IN_FLIGHT)
+        pd = pipelined(api, torch, dense, w, o, d, "branch", W, hdda, args.steps, args.warmup, IN_FLIGHT)
+        pipe = {"streams": IN_FLIGHT, "ms_per_step": pv, "rays_per_s": N / (pv * 1e-3), "samples_per_s": S / (pv * 1e-3),
                 "dense_ms_per_step": pd, "dense_rays_per_s": N / (pd * 1e-3), "speedup_vs_dense": pd / pv,
                 "single_stream_ms_per_step": ms, "gain_over_single_stream": ms / pv,
-                "what": "K back-to-back steps alternating between two streams of the default priority, each "
+                "what": f"K back-to-back steps taking turns on {IN_FLIGHT} streams of the default priority, each "
                         "with its own workspace and outputs, bracketed by events; every step is a whole "
                         "one-call pass over all 640,000 rays"}
     value_ms = pipe["ms_per_step"] if pipe else ms

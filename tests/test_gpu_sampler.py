@@ -484,8 +484,9 @@ def test_voxel_steps_only_on_vdb_grids(small):
 def test_two_batches_in_flight(obj, obj_ref):
     """Consecutive one-call steps alternating between two streams, each with
     its own sampler workspace and outputs and one grid shared read-only, as
-    the benchmark's whole-job figure runs them: every stream's samples equal
-    the oracle's, for the VDB walk and the dense march."""
+    the benchmark's whole-job figures run them (there on two or three
+    streams): every stream's samples equal the oracle's, for the VDB walk
+    and the dense march."""
     o = torch.from_numpy(np.ascontiguousarray(obj.origins)).cuda()
     d = torch.from_numpy(np.ascontiguousarray(obj.dirs)).cuda()
     S = int(obj_ref["offsets"][-1])
